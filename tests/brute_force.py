@@ -1,0 +1,115 @@
+"""Scalar per-node reference of one time step, for tiny lattices only.
+
+Written independently of the vectorised oracle: explicit neighbour index
+arithmetic with modulo wrap, velocity tables typed out here, and the equilibrium
+and correction terms in their closed population-space forms (for D2Q9 these are
+M^-1 of Eq. 27 and of Eq. 29's C; for D3Q19 the same construction rules).  Used
+to pin the oracle on 3x3 .. 5x5 (x5) lattices.
+"""
+
+E2 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+W2 = [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4
+E3 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+      (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+      (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+W3 = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
+
+
+def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot"):
+    """f: dict {(a, node): value}; dims = (nx, ny) or (nx, ny, nz); node = (x, y[, z]).
+    Returns (f_next, fields)."""
+    D = len(dims)
+    E, W = (E2, W2) if D == 2 else (E3, W3)
+    Q = len(E)
+    nodes = [(x, y) for y in range(dims[1]) for x in range(dims[0])] if D == 2 else \
+        [(x, y, z) for z in range(dims[2]) for y in range(dims[1]) for x in range(dims[0])]
+
+    def nb(n, e, s=1):
+        return tuple((n[d] + s * e[d]) % dims[d] for d in range(D))
+
+    def grad(field, n):
+        return [3.0 * sum(W[a] * field[nb(n, E[a])] * E[a][d] for a in range(Q)) for d in range(D)]
+
+    def lap(field, n):
+        return 6.0 * sum(W[a] * (field[nb(n, E[a])] - field[n]) for a in range(1, Q))
+
+    rho = {n: sum(f[(a, n)] for a in range(Q)) for n in nodes}
+    j = {n: [sum(E[a][d] * f[(a, n)] for a in range(Q)) for d in range(D)] for n in nodes}
+    lrho = {n: lap(rho, n) for n in nodes}
+    mu = {n: mu_eos(rho[n]) - kappa * lrho[n] for n in nodes}
+    F = {}
+    for n in nodes:
+        gmu = grad(mu, n)
+        if scheme == "improved":
+            F[n] = [(1 / 3 - rho[n]) * gmu[d] for d in range(D)]
+        elif force_form == "chempot":
+            grho = grad(rho, n)
+            F[n] = [grho[d] / 3 - rho[n] * gmu[d] for d in range(D)]
+    if scheme == "standard" and force_form == "ptensor":
+        grho = {n: grad(rho, n) for n in nodes}
+        P = {}
+        for n in nodes:
+            g2 = sum(x * x for x in grho[n])
+            p = p_eos(rho[n]) - kappa * rho[n] * lrho[n] - 0.5 * kappa * g2
+            P[n] = [[(p if i == k else 0.0) + kappa * grho[n][i] * grho[n][k] for k in range(D)] for i in range(D)]
+        for n in nodes:
+            grh = grho[n]
+            div = []
+            for k in range(D):
+                s = 0.0
+                for a in range(Q):
+                    m = nb(n, E[a])
+                    for i in range(D):
+                        s += 3.0 * W[a] * E[a][i] * P[m][i][k]
+                div.append(s)
+            F[n] = [grh[k] / 3 - div[k] for k in range(D)]
+    u = {n: [(j[n][d] + 0.5 * F[n][d]) / rho[n] for d in range(D)] for n in nodes}
+    pm = {n: ((1 + mu[n]) / 3 if scheme == "improved" else rho[n] / 3) for n in nodes}
+    dcorr = {}
+    if scheme == "improved":
+        psi = [{n: (rho[n] / 3 - pm[n]) * u[n][d] for n in nodes} for d in range(D)]
+        for n in nodes:
+            dcorr[n] = [3.0 * sum(W[a] * psi[d][nb(n, E[a])] * E[a][d] for a in range(Q)) for d in range(D)]
+
+    out = {}
+    for n in nodes:
+        r, uu, FF = rho[n], u[n], F[n]
+        usq = sum(x * x for x in uu)
+        php = pm[n] - r / 3
+        if scheme == "improved":
+            Cii = [3.0 * x for x in dcorr[n]]
+        for a in range(Q):
+            e = E[a]
+            c2 = sum(x * x for x in e)
+            eu = sum(e[d] * uu[d] for d in range(D))
+            feq = W[a] * r * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * usq)
+            if scheme == "improved":
+                rest = 1.0 if a == 0 else 0.0
+                if D == 2:
+                    feq += 3 * php * (W[a] - rest) + 4.5 * php * W[a] * eu * (3 * c2 - 4)
+                else:
+                    feq += 3 * php * (W[a] - rest) + 9.0 * php * W[a] * eu * (3 * c2 - 5)
+            G = W[a] * sum((3 * (e[d] - uu[d]) + 9 * eu * e[d]) * FF[d] for d in range(D))
+            C = 0.0
+            if scheme == "improved":
+                if D == 2:
+                    cx, cy = Cii
+                    if a == 0:
+                        C = -(cx + cy) / 3
+                    elif c2 == 1:
+                        C = (cx - 2 * cy) / 6 if e[0] != 0 else (cy - 2 * cx) / 6
+                    else:
+                        C = (cx + cy) / 6
+                else:
+                    if a == 0:
+                        C = -5 * sum(Cii) / 21
+                    elif c2 == 1:
+                        i = [d for d in range(3) if e[d] != 0][0]
+                        C = (Cii[i] - 6 * (sum(Cii) - Cii[i])) / 42
+                    else:
+                        ii = [d for d in range(3) if e[d] != 0]
+                        k = [d for d in range(3) if e[d] == 0][0]
+                        C = (5 * (Cii[ii[0]] + Cii[ii[1]]) - 2 * Cii[k]) / 42
+            fs = f[(a, n)] - (f[(a, n)] - feq) / tau + (1 - 0.5 / tau) * (G + C)
+            out[(a, nb(n, e))] = fs          # streaming, Eq. 10
+    return out, {"rho": rho, "u": u, "mu": mu, "F": F}
