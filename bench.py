@@ -1,0 +1,212 @@
+"""Throughput benchmark of the fused free-energy LB step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-secondary] [--no-cpu-baseline]
+
+Primary workload (the metric's configuration): D2Q9 512 x 512 periodic lattice,
+Carnahan-Starling droplet of radius 80 at T/Tc = 0.8, kappa = 0.01, tau = 0.8,
+improved scheme, float64.  One step = one fused kernel launch over the lattice
+(pull streaming, rho, mu, forces, correction, collision).  `value` is million
+lattice updates per second over exactly K timed steps (inputs resident in HBM).
+
+`roofline`: algorithmic HBM bytes of the step kernel (read and write each
+population once: 2 * Q * word bytes per node) divided by the kernel's average
+duration from HIP events recorded on the launch stream, against 8 TB/s.
+`cpu_baseline`: the CPU oracle on a bounded number of steps of the same lattice.
+`secondary`: the same measurement for FP32 deviation storage, the standard
+scheme, the 256^3 D3Q19 droplet and a batched coexistence sweep.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline: FP64 plain vs FP32/batched/adjoint, same accuracy"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of secondary names to run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def timed_steps(torch, sim, steps, warmup):
+    """Warm up, capture graphs outside the timed region, then time exactly `steps`
+    steps with HIP events on the launch stream.  Returns ms per step."""
+    sim.step(warmup)
+    sim.prepare(steps)
+    torch.cuda.synchronize()
+    s = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    sim.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure(torch, runtime, inputs, spec, steps, warmup):
+    """Build one workload, time it, return a result record."""
+    p_list, rho0 = spec["params"], spec["rho0"]
+    sim = runtime.LBM(p_list)
+    sim.init(rho0)
+    ms = timed_steps(torch, sim, steps, warmup)
+    nodes = sim.N
+    Q = sim.Q
+    word = 8 if p_list[0].precision == 0 else 4
+    bytes_per_launch = 2 * Q * word * nodes
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    diag = sim.diagnostics()
+    blown = sum(1 for d in diag if d["status"])
+    sim.close()
+    return {
+        "name": spec["name"],
+        "workload": spec["workload"],
+        "mlups": nodes / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms,
+        "nodes": nodes,
+        "bytes_per_lup": 2 * Q * word,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS},
+        "blown_up_lattices": blown,
+        "max_u": max(d["max_u"] for d in diag),
+    }
+
+
+def primary_spec(runtime, inputs, precision="fp64", scheme="improved", T=0.8):
+    m = runtime.maxwell("CS", T)
+    p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=T, kappa=0.01, tau=0.8, scheme=scheme,
+                       precision=precision)
+    rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
+    return {"name": f"d2q9_512_cs_{scheme}_{precision}", "params": [p], "rho0": rho0,
+            "workload": f"D2Q9 512x512 periodic, Carnahan-Starling droplet r=80 W=5, T/Tc={T}, kappa=0.01, "
+                        f"tau=0.8, {scheme} scheme, {precision}"}
+
+
+def d3q19_spec(runtime, inputs):
+    m = runtime.maxwell("vdW", 0.7)
+    p = runtime.params("D3Q19", 256, 256, 256, eos="vdW", T_over_Tc=0.7, kappa=0.02, tau=1.0,
+                       scheme="improved", precision="fp32")
+    rho0 = inputs.droplet((256, 256, 256), m["rho_g"], m["rho_l"], 40.0, 5.0, noise=0.0)
+    return {"name": "d3q19_256_vdw_improved_fp32", "params": [p], "rho0": rho0,
+            "workload": "D3Q19 256^3 periodic, vdW droplet r=40 W=5, T/Tc=0.7, kappa=0.02, tau=1.0, improved, "
+                        "fp32 deviation storage"}
+
+
+def batch_spec(runtime, inputs, count=96, seed=0):
+    specs = inputs.batch_specs(count, seed)
+    ps, rhos = [], []
+    for s in specs:
+        n = s["n"]
+        m = runtime.maxwell("vdW", s["T_over_Tc"])
+        ps.append(runtime.params("D2Q9", n, n, 1, eos="vdW", T_over_Tc=s["T_over_Tc"], kappa=s["kappa"],
+                                 tau=1.0, scheme="improved", precision="fp32"))
+        if s["shape"] == "droplet":
+            rhos.append(inputs.droplet((n, n), m["rho_g"], m["rho_l"], 0.2 * n, 5.0, noise=1e-4, seed=s["seed"]))
+        else:
+            rhos.append(inputs.slab((n, n), m["rho_g"], m["rho_l"], 4.0, noise=1e-4, seed=s["seed"]))
+    return {"name": "batch96_d2q9_fp32", "params": ps, "rho0": np.concatenate([r.ravel() for r in rhos]),
+            "workload": f"{count} D2Q9 lattices n in {{64,128,256,512}} (seed {seed}), slabs/droplets, "
+                        "T/Tc in [0.5,0.95], kappa in [0.005,0.02], tau=1.0, improved, fp32, one launch per step"}
+
+
+def cpu_baseline(torch, inputs, seconds):
+    """The oracle (float64, CPU) on the primary lattice, as many whole steps as fit
+    in about `seconds` (at least 2)."""
+    from oracle import eos as oeos
+    from oracle import model
+
+    threads = os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    E = oeos.CarnahanStarling()
+    m = oeos.maxwell(E, 0.8)
+    rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
+    prm = model.Params(lattice="D2Q9", eos=E, T_over_Tc=0.8, kappa=0.01, tau=0.8, scheme="improved")
+    f = model.init(torch.as_tensor(rho0), prm)
+    f = model.step(f, prm)      # first-call overheads outside the timing
+    n, t0 = 0, time.perf_counter()
+    while True:
+        f = model.step(f, prm)
+        n += 1
+        el = time.perf_counter() - t0
+        if (el >= seconds and n >= 2) or n >= 2000:
+            break
+    return {"value": 512 * 512 * n / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{n} steps of the 512x512 D2Q9 CS droplet (improved, float64), "
+                                        f"{el:.1f} s on the host CPU"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding'); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2008_01473_amd import inputs, runtime
+
+    torch.cuda.set_device(0)
+    prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup)
+    print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step",
+          file=sys.stderr, flush=True)
+    secondary = []
+    if not args.no_secondary:
+        only = set(filter(None, args.only.split(",")))
+        jobs = [
+            ("fp32", lambda: primary_spec(runtime, inputs, precision="fp32"), args.steps),
+            ("standard", lambda: primary_spec(runtime, inputs, scheme="standard"), args.steps),
+            ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),
+            ("batch", lambda: batch_spec(runtime, inputs), max(20, args.steps // 20)),
+        ]
+        for name, mk, k in jobs:
+            if only and name not in only:
+                continue
+            r = measure(torch, runtime, inputs, mk(), k, min(args.warmup, k))
+            r["steps"] = k
+            r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
+            secondary.append(r)
+            print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s)",
+                  file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(torch, inputs, args.cpu_seconds)
+    line = {
+        "metric": METRIC,
+        "value": prim["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": prim["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": prim["workload"], "lattice": "D2Q9", "nodes": prim["nodes"],
+                   "bytes_per_lup": prim["bytes_per_lup"]},
+        "roofline": dict(prim["roofline"], traffic=None),
+        "cpu_baseline": cpu,
+        "secondary": secondary,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) free-energy lattice Boltzmann library.
+ *
+ * The library advances the forcing-based free-energy multiphase lattice
+ * Boltzmann method of Li, Yu & Huang (arXiv:2008.01473) on periodic D2Q9 and
+ * D3Q19 lattices, in the paper's standard scheme (force of Eq. 13, equilibrium
+ * of Eq. 11, collision of Eq. 9) and in its improved scheme (p_m = (1 + mu)/3,
+ * force of Eq. 24, equilibrium of Eq. 27, correction term of Eqs. 28-29), with
+ * the BGK special case Lambda = I / tau of the relaxation matrix (Eq. 8).
+ * The chemical potential is Eq. 2 with the van der Waals free energy of Eq. 30
+ * or a Carnahan-Starling free energy; gradients use the isotropic stencil of
+ * Eq. 17 and the Laplacian its isotropic counterpart with the same weights.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: LBM_OK (0) or a negative LBM_ERR_* code; no C++ exception
+ *     crosses this boundary.  lbm_error_string() describes a code, and
+ *     lbm_last_error() the most recent failure of the calling thread in words.
+ *   - Device memory: every large buffer (distributions, workspace, input and
+ *     output fields) is allocated and owned by the caller.  The library owns
+ *     only the handle, a few small host tables and the HIP graphs it captures.
+ *   - Streams: work is enqueued, asynchronously, on the hipStream_t given to
+ *     lbm_create / lbm_create_batch (NULL = the null stream).  Only
+ *     lbm_diagnostics, lbm_maxwell and the size queries block the host.
+ *   - Field layout across the boundary: float64, structure of arrays, row-major
+ *     with x fastest.  A scalar field of one lattice has nz*ny*nx entries
+ *     indexed (z*ny + y)*nx + x (nz = 1 in 2D); a vector field has D such
+ *     blocks (component x first).  In a batch the lattices follow one another
+ *     in creation order, each starting at its node offset (lbm_node_offset).
+ *   - Distribution layout (lbm_get_f / lbm_set_f): Q blocks of one scalar
+ *     field each, population a at block a.  Velocity order
+ *       D2Q9 : rest; E, N, W, S; NE, NW, SW, SE
+ *              (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *       D3Q19: rest; +x, -x, +y, -y, +z, -z;
+ *              (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1)
+ *              (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *     These are the populations f_a(x, t) after streaming (Eq. 10) and before
+ *     the next collision, i.e. those from which Eq. 12 computes rho and u.
+ *   - Time level: a handle holds one time level t (0 after lbm_init); each
+ *     lbm_step advances it by one.  lbm_moments returns the fields at t.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_status_code {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,          /* invalid argument or parameter combination        */
+    LBM_ERR_UNSUPPORTED = -2,  /* valid request this build does not implement      */
+    LBM_ERR_HIP = -3,          /* a HIP runtime call failed                        */
+    LBM_ERR_BLOWUP = -4,       /* a lattice produced NaN/Inf or left the EOS domain */
+    LBM_ERR_DOMAIN = -5,       /* no liquid-gas coexistence (e.g. T >= T_c)        */
+    LBM_ERR_STATE = -6         /* call out of order (e.g. step before bind/init)   */
+};
+
+enum lbm_lattice   { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum lbm_eos       { LBM_EOS_VDW = 0, LBM_EOS_CS = 1 };
+enum lbm_scheme    { LBM_STANDARD = 0, LBM_IMPROVED = 1 };
+enum lbm_force     { LBM_FORCE_CHEMPOT = 0, LBM_FORCE_PTENSOR = 1 };
+enum lbm_precision { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+
+/* Per-lattice blow-up flags, OR-ed into lbm_diag.status. */
+enum lbm_blowup_bits {
+    LBM_BLOWUP_NONFINITE = 1,  /* rho, u or a population is NaN or Inf      */
+    LBM_BLOWUP_RHO_NONPOS = 2, /* rho <= 0                                  */
+    LBM_BLOWUP_RHO_MAX = 4     /* rho >= packing limit (1/b vdW, 4/b CS)    */
+};
+
+/*
+ * Physical and numerical parameters of one lattice.
+ *   lattice      LBM_D2Q9 or LBM_D3Q19 (nz must be 1 for D2Q9)
+ *   nx, ny, nz   lattice extent, periodic in every direction, each >= 1
+ *   eos          LBM_EOS_VDW: E_f = rho R T ln[rho/(1 - b rho)] - a rho^2 (Eq. 30)
+ *                LBM_EOS_CS : E_f = rho R T [ln rho + (4h - 3h^2)/(1-h)^2] - a rho^2,
+ *                             h = b rho / 4 (Carnahan-Starling; not in the paper)
+ *   a, b, R      EOS constants (the paper: a = 9/392, b = 2/21, R = 1)
+ *   T_over_Tc    reduced temperature; T_c is 8a/(27Rb) for vdW and the numerical
+ *                critical point of the CS free energy
+ *   kappa        interfacial coefficient of Eq. 1 (> 0)
+ *   tau          BGK relaxation time, Lambda = I/tau (> 0.5)
+ *   scheme       LBM_STANDARD (Eq. 13) or LBM_IMPROVED (Eq. 24, 27, 28-29)
+ *   force_form   LBM_FORCE_CHEMPOT (rho grad mu) or LBM_FORCE_PTENSOR (div P of
+ *                Eqs. 4-5); PTENSOR requires LBM_STANDARD
+ *   precision    LBM_FP64: float64 storage and arithmetic.
+ *                LBM_FP32_DEV: float32 storage of f - fbar and float32 arithmetic,
+ *                fbar the rest equilibrium at (rho_ref, u = 0, p_m = pm_ref);
+ *                mass sums stay float64.
+ *   rho_ref, pm_ref  FP32_DEV reference state; values <= 0 select the defaults
+ *                rho_ref = (rho_g + rho_l)/2 of the Maxwell construction and
+ *                pm_ref = (1 + mu_sat)/3 (improved) or rho_ref/3 (standard).
+ * All lattices of one batch must share lattice, scheme, force_form, precision.
+ */
+typedef struct {
+    int lattice, nx, ny, nz;
+    int eos;
+    double a, b, R;
+    double T_over_Tc, kappa, tau;
+    int scheme, force_form, precision;
+    double rho_ref, pm_ref;
+} lbm_params;
+
+/*
+ * Diagnostics of one lattice at one time level (float64 sums over the nodes in
+ * a fixed order, so repeated runs give identical values):
+ *   mass = sum rho,  mom = sum (j + F/2) = sum rho u (mom[2] = 0 in 2D),
+ *   max_u = max |u|, mu_min / mu_max over the lattice, step = time level,
+ *   status = OR of lbm_blowup_bits seen since lbm_init (0 = healthy).
+ */
+typedef struct {
+    double mass, mom[3], max_u, mu_min, mu_max;
+    long long step;
+    int status, reserved;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Create a handle for one lattice.  Checks the parameters, solves the Maxwell
+ * construction on the host (for the FP32_DEV defaults) and plans the tiling.
+ * No device memory is allocated.  *out receives the handle. */
+int lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
+
+/* Create a handle for `count` independent lattices advanced together by one
+ * kernel launch per step (sizes, EOS constants, T, kappa and tau may differ). */
+int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx** out);
+
+/* Bytes of one distribution buffer (all lattices) and of the workspace the
+ * caller must allocate; alignment of both: 256 bytes. */
+size_t lbm_state_bytes(const lbm_ctx* h);
+size_t lbm_workspace_bytes(const lbm_ctx* h);
+
+/* Total nodes of the handle and the node offset of lattice i in field arrays. */
+long long lbm_num_nodes(const lbm_ctx* h);
+long long lbm_node_offset(const lbm_ctx* h, int i);
+int lbm_count(const lbm_ctx* h);
+
+/* Attach caller-owned device memory: two distribution buffers of
+ * lbm_state_bytes each and one workspace of lbm_workspace_bytes.  Uploads the
+ * small parameter and tile tables into the workspace (asynchronously). */
+int lbm_bind(lbm_ctx* h, void* f_a, void* f_b, void* workspace);
+
+/* Set time level 0: f = f_eq(rho0, u0) with the scheme's equilibrium (Eq. 11
+ * or Eq. 27; p_m from mu(rho0) including -kappa lap(rho0)).  rho0: device,
+ * float64, lbm_num_nodes entries; u0: device, float64, D blocks, or NULL for
+ * u0 = 0.  Clears the blow-up flags. */
+int lbm_init(lbm_ctx* h, const double* rho0, const double* u0);
+
+/* Advance n >= 0 steps (Eqs. 7-10 with the scheme's force and sources), one
+ * fused kernel per step; n >= 2 steps are replayed from a captured HIP graph.
+ * Lattices whose blow-up flags are set are skipped from then on. */
+int lbm_step(lbm_ctx* h, int n);
+
+/* Capture, without running them, the HIP graphs that lbm_step(h, n) will replay
+ * from the current buffer parity, so that a later lbm_step(h, n) launches only
+ * (e.g. outside a timed region).  Enqueues no work. */
+int lbm_prepare_steps(lbm_ctx* h, int n);
+
+/* Fields at the current time level (Eq. 12, Eq. 2): rho [N], u [D][N], mu [N];
+ * device float64 pointers, any may be NULL.  Also refreshes the diagnostics. */
+int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu);
+
+/* Copy the diagnostics of every lattice (count entries) to host memory.  They
+ * refer to the time level of the most recent lbm_step input or lbm_moments
+ * call (lbm_diag.step).  Blocks until the stream has finished.  Returns
+ * LBM_ERR_BLOWUP if any lattice has its status set (out is still filled). */
+int lbm_diagnostics(lbm_ctx* h, lbm_diag* out_host);
+
+/* Populations f_a(x, t) at the current time level as float64 (layout above),
+ * and the inverse: replace the state by the given populations. */
+int lbm_get_f(lbm_ctx* h, double* f_dev);
+int lbm_set_f(lbm_ctx* h, const double* f_dev);
+
+/* Raw checkpoint of the current state (lbm_state_bytes, device to device) and
+ * its restore; the time level is saved/restored through *step. */
+int lbm_get_state(lbm_ctx* h, void* dst_dev, long long* step);
+int lbm_set_state(lbm_ctx* h, const void* src_dev, long long step);
+
+/* Time level of the handle. */
+long long lbm_time(const lbm_ctx* h);
+
+/* Maxwell construction (equal mu_EOS and p_EOS) of the chosen EOS at T/T_c, on
+ * the host in float64.  Returns LBM_ERR_DOMAIN when there is no coexistence. */
+int lbm_maxwell(int eos, double a, double b, double R, double T_over_Tc,
+                double* rho_g, double* rho_l, double* mu_sat, double* p_sat);
+
+/* Critical temperature of the chosen EOS (host, float64). */
+double lbm_critical_temperature(int eos, double a, double b, double R);
+
+/* Kernel tuning: tile shape index (see lbm_tile_shapes) and whether lbm_step
+ * replays HIP graphs (1, default) or launches one kernel per step (0). */
+int lbm_set_tile_shape(lbm_ctx* h, int shape_index);
+int lbm_get_tile_shape(const lbm_ctx* h);
+int lbm_num_tile_shapes(const lbm_ctx* h);
+int lbm_describe_tile_shape(const lbm_ctx* h, int shape_index, int* bx, int* by, int* bz);
+int lbm_set_use_graphs(lbm_ctx* h, int on);
+
+/* Pick the fastest tile shape by timing `steps` steps of each on the current
+ * state (the state is restored afterwards); returns the chosen index. */
+int lbm_autotune(lbm_ctx* h, int steps, void* scratch_state);
+
+/* Measurement helper: copy `bytes` from src to dst on the handle-less stream
+ * `hip_stream` with a plain vectorised copy kernel (used to calibrate traffic
+ * counters against a kernel of known size). */
+int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+const char* lbm_error_string(int code);
+const char* lbm_last_error(void);
+void lbm_destroy(lbm_ctx* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,661 @@
+// Host runtime behind the C ABI of include/lbm.h: parameter checks, tiling
+// plans, workspace layout, kernel launches, HIP graph replay of many steps,
+// diagnostics read-back and the tile-shape autotuner.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "host_thermo.hpp"
+#include "lbm_shared.hpp"
+
+namespace lbm {
+hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
+                            bool fields);
+hipError_t d2q9_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                            long long total, hipStream_t s, int precision, int variant);
+hipError_t d2q9_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
+                               hipStream_t s, int precision, bool get);
+hipError_t d3q19_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
+                             bool fields);
+hipError_t d3q19_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                             long long total, hipStream_t s, int precision, int variant);
+hipError_t d3q19_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
+                                hipStream_t s, int precision, bool get);
+hipError_t launch_finalize(const DiagPartial* partial, const LatticeRec* recs, const unsigned* status,
+                           DiagOut* out, int nlat, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+extern const int kD2Q9Shapes[][2];
+extern const int kNumD2Q9Shapes;
+extern const int kD3Q19Shapes[][2];
+extern const int kNumD3Q19Shapes;
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(LBM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kGraphChunk = 256;   // even, so replaying a chunk keeps the buffer parity
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<lbm_params> params;
+    int lattice = 0, Q = 9, D = 2, variant = 0, precision = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<LatticeRec> recs;
+    std::vector<Tile> tiles;
+    int shape = 0;
+    int zchunk_override = 0;
+    long long field_total = 0, state_nodes = 0;
+    size_t state_bytes = 0, ws_bytes = 0;
+    size_t off_recs = 0, off_tiles = 0, off_partial = 0, off_status = 0, off_diag = 0;
+    int max_tiles = 0;
+    char* ws = nullptr;
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    long long t = 0, t_diag = -1;
+    bool bound = false, inited = false;
+    bool use_graphs = true;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+
+    int num_shapes() const { return lattice == LBM_D2Q9 ? kNumD2Q9Shapes : kNumD3Q19Shapes; }
+    void shape_dims(int s, int& bx, int& by) const {
+        if (lattice == LBM_D2Q9) {
+            bx = kD2Q9Shapes[s][0];
+            by = kD2Q9Shapes[s][1];
+        } else {
+            bx = kD3Q19Shapes[s][0];
+            by = kD3Q19Shapes[s][1];
+        }
+    }
+    LatticeRec* d_recs() const { return reinterpret_cast<LatticeRec*>(ws + off_recs); }
+    Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + off_tiles); }
+    DiagPartial* d_partial() const { return reinterpret_cast<DiagPartial*>(ws + off_partial); }
+    unsigned* d_status() const { return reinterpret_cast<unsigned*>(ws + off_status); }
+    DiagOut* d_diag() const { return reinterpret_cast<DiagOut*>(ws + off_diag); }
+    int zchunk_for(int s) const;
+    std::vector<Tile> plan(int s, std::vector<LatticeRec>& rr) const;
+    void drop_graphs() {
+        for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+};
+
+int lbm_ctx::zchunk_for(int s) const {
+    if (lattice == LBM_D2Q9) return 1;
+    if (zchunk_override > 0) return zchunk_override;
+    int bx, by;
+    shape_dims(s, bx, by);
+    long long cols = 0;
+    int nzmax = 1;
+    for (const auto& p : params) {
+        cols += (long long)((p.nx + bx - 1) / bx) * ((p.ny + by - 1) / by);
+        nzmax = std::max(nzmax, p.nz);
+    }
+    // aim for about 4 work groups per compute unit (256 CUs), chunks of >= 16 slices
+    const long long want = 1024;
+    int chunks = (int)std::max<long long>(1, (want + cols - 1) / cols);
+    int zc = (nzmax + chunks - 1) / chunks;
+    zc = std::max(zc, std::min(16, nzmax));
+    return zc;
+}
+
+std::vector<Tile> lbm_ctx::plan(int s, std::vector<LatticeRec>& rr) const {
+    int bx, by;
+    shape_dims(s, bx, by);
+    const int zc = zchunk_for(s);
+    std::vector<Tile> out;
+    for (size_t L = 0; L < rr.size(); ++L) {
+        LatticeRec& R = rr[L];
+        R.slow_x = R.nx < bx + 8;
+        R.slow_y = R.ny < by + 8;
+        R.slow_z = R.nz < 8;
+        R.tile_begin = (int)out.size();
+        const int ntx = (R.nx + bx - 1) / bx, nty = (R.ny + by - 1) / by;
+        const int nzc = (lattice == LBM_D2Q9) ? 1 : (R.nz + zc - 1) / zc;
+        for (int kz = 0; kz < nzc; ++kz)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) {
+                    Tile t{};
+                    t.lat = (int)L;
+                    t.x0 = tx * bx;
+                    t.y0 = ty * by;
+                    t.z0 = (lattice == LBM_D2Q9) ? 0 : kz * zc;
+                    t.zn = (lattice == LBM_D2Q9) ? 1 : std::min(zc, R.nz - kz * zc);
+                    out.push_back(t);
+                }
+        R.tile_end = (int)out.size();
+    }
+    return out;
+}
+
+namespace {
+
+int check_params(const lbm_params& p) {
+    if (p.lattice != LBM_D2Q9 && p.lattice != LBM_D3Q19) return fail(LBM_ERR_ARG, "lattice must be D2Q9 or D3Q19");
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(LBM_ERR_ARG, "lattice extents must be >= 1");
+    if (p.lattice == LBM_D2Q9 && p.nz != 1) return fail(LBM_ERR_ARG, "D2Q9 requires nz == 1");
+    const long long n = (long long)p.nx * p.ny * p.nz;
+    if (n * (p.lattice == LBM_D2Q9 ? 9 : 19) >= (1LL << 31))
+        return fail(LBM_ERR_UNSUPPORTED, "one lattice may hold at most 2^31 populations");
+    if (p.eos != LBM_EOS_VDW && p.eos != LBM_EOS_CS) return fail(LBM_ERR_ARG, "eos must be VDW or CS");
+    if (!(p.a >= 0) || !(p.b > 0) || !(p.R > 0)) return fail(LBM_ERR_ARG, "EOS constants need a >= 0, b > 0, R > 0");
+    if (!(p.T_over_Tc > 0)) return fail(LBM_ERR_ARG, "T_over_Tc must be > 0");
+    if (!(p.kappa >= 0)) return fail(LBM_ERR_ARG, "kappa must be >= 0");
+    if (!(p.tau > 0.5)) return fail(LBM_ERR_ARG, "tau must be > 0.5");
+    if (p.scheme != LBM_STANDARD && p.scheme != LBM_IMPROVED) return fail(LBM_ERR_ARG, "bad scheme");
+    if (p.force_form != LBM_FORCE_CHEMPOT && p.force_form != LBM_FORCE_PTENSOR) return fail(LBM_ERR_ARG, "bad force form");
+    if (p.force_form == LBM_FORCE_PTENSOR && p.scheme != LBM_STANDARD)
+        return fail(LBM_ERR_ARG, "the pressure-tensor force is defined for the standard scheme only");
+    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return fail(LBM_ERR_ARG, "bad precision");
+    if (p.a == 0) return fail(LBM_ERR_ARG, "a must be > 0 (T_c is proportional to a)");
+    return LBM_OK;
+}
+
+LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
+    LatticeRec R;
+    std::memset(&R, 0, sizeof(R));
+    R.nx = p.nx;
+    R.ny = p.ny;
+    R.nz = p.nz;
+    R.eos = p.eos;
+    R.q = Q;
+    R.nnodes = (long long)p.nx * p.ny * p.nz;
+    R.a = p.a;
+    R.b = p.b;
+    R.RT = p.R * p.T_over_Tc * host::critical_temperature(p.eos, p.a, p.b, p.R);
+    R.kappa = p.kappa;
+    R.omega = 1.0 / p.tau;
+    R.rho_max = host::rho_limit(p.eos, p.b);
+    if (p.precision == LBM_FP64) {
+        R.rho_ref = 0.0;
+        R.pm_ref = 0.0;
+        R.mu_ref = -1.0;     // so that p_m - pm_ref = (mu - mu_ref)/3 = p_m
+        return R;
+    }
+    double rho_ref = p.rho_ref, pm_ref = p.pm_ref;
+    if (!(rho_ref > 0) || !(pm_ref > 0)) {
+        double rg, rl, mu, ps;
+        double T = R.RT / p.R;
+        double rr, mm;
+        if (host::maxwell(p.eos, p.a, p.b, p.R, p.T_over_Tc, &rg, &rl, &mu, &ps) == 0) {
+            rr = 0.5 * (rg + rl);
+            mm = mu;
+        } else {   // no coexistence: single-phase reference at the critical density
+            rr = p.eos == LBM_EOS_VDW ? 1.0 / (3.0 * p.b) : 0.5217755367698157 / p.b;
+            mm = host::mu_eos(p.eos, p.a, p.b, p.R, T, rr);
+        }
+        if (!(rho_ref > 0)) rho_ref = rr;
+        if (!(pm_ref > 0)) pm_ref = (variant == kImproved) ? (1.0 + mm) / 3.0 : rho_ref / 3.0;
+    }
+    R.rho_ref = rho_ref;
+    R.pm_ref = pm_ref;
+    R.mu_ref = 3.0 * pm_ref - 1.0;
+    if (variant != kImproved) R.pm_ref = rho_ref / 3.0;
+    const double pmr = R.pm_ref;
+    if (Q == 9) {
+        R.fbar[0] = rho_ref - 5.0 * pmr / 3.0;
+        for (int a = 1; a < 5; ++a) R.fbar[a] = pmr / 3.0;
+        for (int a = 5; a < 9; ++a) R.fbar[a] = pmr / 12.0;
+    } else {
+        R.fbar[0] = rho_ref - 2.0 * pmr;
+        for (int a = 1; a < 7; ++a) R.fbar[a] = pmr / 6.0;
+        for (int a = 7; a < 19; ++a) R.fbar[a] = pmr / 12.0;
+    }
+    return R;
+}
+
+hipError_t launch_step(lbm_ctx* h, const StepArgs& a, bool fields, hipStream_t s) {
+    const int ntiles = (int)h->tiles.size();
+    const int per = (ntiles + 7) / 8;
+    StepArgs b = a;
+    b.ntiles = ntiles;
+    b.tiles_per_xcd = per;
+    const int grid = 8 * per;
+    if (grid == 0) return hipSuccess;
+    if (h->lattice == LBM_D2Q9) return d2q9_launch_step(b, grid, s, h->precision, h->variant, h->shape, fields);
+    return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->shape, fields);
+}
+
+StepArgs base_args(lbm_ctx* h) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.recs = h->d_recs();
+    a.tiles = h->d_tiles();
+    a.partial = h->d_partial();
+    a.status = h->d_status();
+    a.field_total = h->field_total;
+    return a;
+}
+
+int upload_tables(lbm_ctx* h) {
+    HIP_TRY(hipMemcpyAsync(h->d_recs(), h->recs.data(), h->recs.size() * sizeof(LatticeRec), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_tiles(), h->tiles.data(), h->tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int enqueue_steps(lbm_ctx* h, int n, hipStream_t s) {
+    for (int i = 0; i < n; ++i) {
+        StepArgs a = base_args(h);
+        a.src = h->buf[h->cur];
+        a.dst = h->buf[h->cur ^ 1];
+        HIP_TRY(launch_step(h, a, false, s));
+        h->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+int graph_for(lbm_ctx* h, int n, hipGraphExec_t* out) {
+    auto key = std::make_pair(n, h->cur);
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        *out = it->second;
+        return LBM_OK;
+    }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const int saved = h->cur;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_steps(h, n, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    h->cur = saved;
+    if (rc != LBM_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->graphs[key] = ex;
+    *out = ex;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_error_string(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_ERR_ARG: return "invalid argument";
+        case LBM_ERR_UNSUPPORTED: return "unsupported";
+        case LBM_ERR_HIP: return "HIP runtime error";
+        case LBM_ERR_BLOWUP: return "lattice blew up (NaN/Inf or density out of range)";
+        case LBM_ERR_DOMAIN: return "no liquid-gas coexistence at this temperature";
+        case LBM_ERR_STATE: return "call out of order";
+        default: return "unknown error";
+    }
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx** out) {
+    if (!p || !out || count < 1) return fail(LBM_ERR_ARG, "null argument or count < 1");
+    *out = nullptr;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_params(p[i]);
+        if (rc != LBM_OK) return rc;
+        if (p[i].lattice != p[0].lattice || p[i].scheme != p[0].scheme || p[i].force_form != p[0].force_form ||
+            p[i].precision != p[0].precision)
+            return fail(LBM_ERR_ARG, "lattices of one batch must share lattice, scheme, force form and precision");
+    }
+    lbm_ctx* h = new (std::nothrow) lbm_ctx();
+    if (!h) return fail(LBM_ERR_ARG, "out of host memory");
+    h->params.assign(p, p + count);
+    h->lattice = p[0].lattice;
+    h->Q = h->lattice == LBM_D2Q9 ? 9 : 19;
+    h->D = h->lattice == LBM_D2Q9 ? 2 : 3;
+    h->variant = p[0].scheme == LBM_IMPROVED ? kImproved : (p[0].force_form == LBM_FORCE_PTENSOR ? kStdPtensor
+                                                                                                : kStdChempot);
+    h->precision = p[0].precision;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    long long foff = 0, soff = 0;
+    for (int i = 0; i < count; ++i) {
+        LatticeRec R = make_rec(p[i], h->variant, h->Q);
+        R.field_offset = foff;
+        R.state_offset = soff;
+        foff += R.nnodes;
+        soff += (R.nnodes + 63) / 64 * 64;
+        h->recs.push_back(R);
+    }
+    h->field_total = foff;
+    h->state_nodes = soff;
+    const size_t word = h->precision == LBM_FP64 ? 8 : 4;
+    h->state_bytes = align256((size_t)soff * h->Q * word);
+    // the largest tile list over all shapes, so that re-tiling fits the workspace
+    for (int s = 0; s < h->num_shapes(); ++s) {
+        std::vector<LatticeRec> rr = h->recs;
+        h->max_tiles = std::max<int>(h->max_tiles, (int)h->plan(s, rr).size());
+    }
+    h->max_tiles = std::max(h->max_tiles, 4 * h->max_tiles);   // room for smaller z-chunks
+    h->shape = 0;
+    h->tiles = h->plan(h->shape, h->recs);
+    size_t o = 0;
+    h->off_recs = o;
+    o = align256(o + count * sizeof(LatticeRec));
+    h->off_tiles = o;
+    o = align256(o + (size_t)h->max_tiles * sizeof(Tile));
+    h->off_partial = o;
+    o = align256(o + (size_t)h->max_tiles * sizeof(DiagPartial));
+    h->off_status = o;
+    o = align256(o + count * sizeof(unsigned));
+    h->off_diag = o;
+    o = align256(o + count * sizeof(DiagOut));
+    h->ws_bytes = o;
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out) { return lbm_create_batch(p, 1, hip_stream, out); }
+
+size_t lbm_state_bytes(const lbm_ctx* h) { return h ? h->state_bytes : 0; }
+size_t lbm_workspace_bytes(const lbm_ctx* h) { return h ? h->ws_bytes : 0; }
+long long lbm_num_nodes(const lbm_ctx* h) { return h ? h->field_total : 0; }
+int lbm_count(const lbm_ctx* h) { return h ? (int)h->recs.size() : 0; }
+long long lbm_node_offset(const lbm_ctx* h, int i) {
+    if (!h || i < 0 || i >= (int)h->recs.size()) return -1;
+    return h->recs[i].field_offset;
+}
+long long lbm_time(const lbm_ctx* h) { return h ? h->t : -1; }
+
+int lbm_bind(lbm_ctx* h, void* f_a, void* f_b, void* workspace) {
+    if (!h || !f_a || !f_b || !workspace) return fail(LBM_ERR_ARG, "null argument");
+    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)workspace) & 255)
+        return fail(LBM_ERR_ARG, "buffers must be 256-byte aligned");
+    h->drop_graphs();
+    h->buf[0] = f_a;
+    h->buf[1] = f_b;
+    h->ws = reinterpret_cast<char*>(workspace);
+    h->cur = 0;
+    int rc = upload_tables(h);
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->bound = true;
+    h->inited = false;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx* h, const double* rho0, const double* u0) {
+    if (!h || !rho0) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    h->cur = 0;
+    if (h->lattice == LBM_D2Q9)
+        HIP_TRY(d2q9_launch_init(h->buf[0], h->d_recs(), (int)h->recs.size(), rho0, u0, h->field_total, h->stream,
+                                 h->precision, h->variant));
+    else
+        HIP_TRY(d3q19_launch_init(h->buf[0], h->d_recs(), (int)h->recs.size(), rho0, u0, h->field_total, h->stream,
+                                  h->precision, h->variant));
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->t = 0;
+    h->t_diag = -1;
+    h->inited = true;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* h, int n) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (n < 0) return fail(LBM_ERR_ARG, "n must be >= 0");
+    if (!h->inited) return fail(LBM_ERR_STATE, "lbm_init or lbm_set_f first");
+    if (n == 0) return LBM_OK;
+    const long long t0 = h->t;
+    if (!h->use_graphs || n < 2) {
+        int rc = enqueue_steps(h, n, h->stream);
+        if (rc != LBM_OK) return rc;
+    } else {
+        int left = n;
+        while (left >= 2) {
+            const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
+            hipGraphExec_t ex;
+            int rc = graph_for(h, len, &ex);
+            if (rc != LBM_OK) return rc;
+            HIP_TRY(hipGraphLaunch(ex, h->stream));
+            left -= len;     // len is even: the current buffer is unchanged
+        }
+        if (left) {
+            int rc = enqueue_steps(h, left, h->stream);
+            if (rc != LBM_OK) return rc;
+        }
+    }
+    h->t = t0 + n;
+    h->t_diag = h->t - 1;
+    return LBM_OK;
+}
+
+int lbm_prepare_steps(lbm_ctx* h, int n) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (n < 0) return fail(LBM_ERR_ARG, "n must be >= 0");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    if (!h->use_graphs) return LBM_OK;
+    int left = n;
+    while (left >= 2) {
+        const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
+        hipGraphExec_t ex;
+        int rc = graph_for(h, len, &ex);
+        if (rc != LBM_OK) return rc;
+        left -= len;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "lbm_init or lbm_set_f first");
+    StepArgs a = base_args(h);
+    a.src = h->buf[h->cur];
+    a.dst = nullptr;
+    a.rho_out = rho;
+    a.u_out = u;
+    a.mu_out = mu;
+    HIP_TRY(launch_step(h, a, true, h->stream));
+    h->t_diag = h->t;
+    return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
+    if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->inited || h->t_diag < 0) return fail(LBM_ERR_STATE, "no diagnostics yet (step or moments first)");
+    const int n = (int)h->recs.size();
+    HIP_TRY(launch_finalize(h->d_partial(), h->d_recs(), h->d_status(), h->d_diag(), n, h->stream));
+    std::vector<DiagOut> tmp(n);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), h->d_diag(), n * sizeof(DiagOut), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int rc = LBM_OK;
+    for (int i = 0; i < n; ++i) {
+        out[i].mass = tmp[i].mass;
+        out[i].mom[0] = tmp[i].momx;
+        out[i].mom[1] = tmp[i].momy;
+        out[i].mom[2] = tmp[i].momz;
+        out[i].max_u = tmp[i].umax;
+        out[i].mu_min = tmp[i].mumin;
+        out[i].mu_max = tmp[i].mumax;
+        out[i].step = h->t_diag;
+        out[i].status = (int)tmp[i].status;
+        out[i].reserved = 0;
+        if (tmp[i].status) rc = LBM_ERR_BLOWUP;
+    }
+    if (rc != LBM_OK) fail(rc, "at least one lattice has its blow-up flags set");
+    return rc;
+}
+
+int lbm_get_f(lbm_ctx* h, double* f) {
+    if (!h || !f) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "no state");
+    if (h->lattice == LBM_D2Q9)
+        HIP_TRY(d2q9_launch_convert(h->buf[h->cur], h->d_recs(), (int)h->recs.size(), f, h->field_total, h->stream,
+                                    h->precision, true));
+    else
+        HIP_TRY(d3q19_launch_convert(h->buf[h->cur], h->d_recs(), (int)h->recs.size(), f, h->field_total, h->stream,
+                                     h->precision, true));
+    return LBM_OK;
+}
+
+int lbm_set_f(lbm_ctx* h, const double* f) {
+    if (!h || !f) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    if (h->lattice == LBM_D2Q9)
+        HIP_TRY(d2q9_launch_convert(h->buf[h->cur], h->d_recs(), (int)h->recs.size(), const_cast<double*>(f),
+                                    h->field_total, h->stream, h->precision, false));
+    else
+        HIP_TRY(d3q19_launch_convert(h->buf[h->cur], h->d_recs(), (int)h->recs.size(), const_cast<double*>(f),
+                                     h->field_total, h->stream, h->precision, false));
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->inited = true;
+    h->t_diag = -1;
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* h, void* dst, long long* step) {
+    if (!h || !dst) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "no state");
+    HIP_TRY(hipMemcpyAsync(dst, h->buf[h->cur], h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (step) *step = h->t;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* h, const void* src, long long step) {
+    if (!h || !src) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    HIP_TRY(hipMemcpyAsync(h->buf[h->cur], src, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->t = step;
+    h->t_diag = -1;
+    h->inited = true;
+    return LBM_OK;
+}
+
+int lbm_maxwell(int eos, double a, double b, double R, double T_over_Tc, double* rho_g, double* rho_l,
+                double* mu_sat, double* p_sat) {
+    if (eos != LBM_EOS_VDW && eos != LBM_EOS_CS) return fail(LBM_ERR_ARG, "bad eos");
+    const int rc = host::maxwell(eos, a, b, R, T_over_Tc, rho_g, rho_l, mu_sat, p_sat);
+    if (rc == -1) return fail(LBM_ERR_ARG, "EOS constants and T_over_Tc must be positive");
+    if (rc != 0) return fail(LBM_ERR_DOMAIN, "no liquid-gas coexistence at this temperature");
+    return LBM_OK;
+}
+
+double lbm_critical_temperature(int eos, double a, double b, double R) {
+    return host::critical_temperature(eos, a, b, R);
+}
+
+int lbm_num_tile_shapes(const lbm_ctx* h) { return h ? h->num_shapes() : 0; }
+int lbm_get_tile_shape(const lbm_ctx* h) { return h ? h->shape : -1; }
+
+int lbm_describe_tile_shape(const lbm_ctx* h, int s, int* bx, int* by, int* bz) {
+    if (!h || s < 0 || s >= h->num_shapes()) return fail(LBM_ERR_ARG, "bad shape index");
+    int x, y;
+    h->shape_dims(s, x, y);
+    if (bx) *bx = x;
+    if (by) *by = y;
+    if (bz) *bz = h->zchunk_for(s);
+    return LBM_OK;
+}
+
+int lbm_set_tile_shape(lbm_ctx* h, int s) {
+    if (!h || s < 0 || s >= h->num_shapes()) return fail(LBM_ERR_ARG, "bad shape index");
+    std::vector<LatticeRec> rr = h->recs;
+    std::vector<Tile> tt = h->plan(s, rr);
+    if ((int)tt.size() > h->max_tiles) return fail(LBM_ERR_UNSUPPORTED, "tile list does not fit the workspace");
+    if (h->bound) HIP_TRY(hipStreamSynchronize(h->stream));
+    h->recs = rr;
+    h->tiles = tt;
+    h->shape = s;
+    h->drop_graphs();
+    if (h->bound) return upload_tables(h);
+    return LBM_OK;
+}
+
+int lbm_set_use_graphs(lbm_ctx* h, int on) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    h->use_graphs = on != 0;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
+    if (!h || !scratch || steps < 1) return fail(LBM_ERR_ARG, "bad argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "lbm_init first");
+    long long t0;
+    int rc = lbm_get_state(h, scratch, &t0);
+    if (rc != LBM_OK) return rc;
+    const int cur0 = h->cur;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = h->shape;
+    float best_ms = 1e30f;
+    for (int s = 0; s < h->num_shapes(); ++s) {
+        rc = lbm_set_tile_shape(h, s);
+        if (rc != LBM_OK) continue;
+        rc = lbm_step(h, 2);                 // warm-up and graph capture
+        if (rc != LBM_OK) break;
+        HIP_TRY(hipEventRecord(e0, h->stream));
+        rc = lbm_step(h, steps);
+        if (rc != LBM_OK) break;
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+        h->cur = cur0;
+        HIP_TRY(hipMemcpyAsync(h->buf[h->cur], scratch, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+        h->t = t0;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    rc = lbm_set_tile_shape(h, best);
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->t_diag = -1;
+    return best;
+}
+
+int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    if (!dst || !src) return fail(LBM_ERR_ARG, "null argument");
+    HIP_TRY(launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream)));
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* h) {
+    if (!h) return;
+    h->drop_graphs();
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+}  // extern "C"

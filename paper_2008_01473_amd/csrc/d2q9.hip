@@ -1,0 +1,495 @@
+// D2Q9 kernels: the fused time step (one work group per output tile, halos
+// recomputed in LDS), the initialisation from (rho0, u0), and conversion of
+// the stored state to and from post-streaming populations.
+//
+// Velocity order: 0 rest; 1 E (1,0); 2 N (0,1); 3 W (-1,0); 4 S (0,-1);
+//                 5 NE (1,1); 6 NW (-1,1); 7 SW (-1,-1); 8 SE (1,-1).
+// State layout: one buffer per time level holding, for population a at node x,
+// the post-collision value f*_a(x) of the previous step (before streaming);
+// population a of lattice L lives at state_offset(L)*9 + a*nnodes(L) + y*nx + x.
+// A step pulls f_a(x) = f*_a(x - e_a) (Eq. 10) and writes f*_a(x) of the new
+// time level at x itself.  In FP32 deviation mode the stored value is
+// f - fbar with fbar the reference rest equilibrium of the lattice.
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+#include "lbm_shared.hpp"
+
+namespace lbm {
+namespace d2q9 {
+
+// Pull the nine populations arriving at (xc, yc): f_a(x) = f*_a(x - e_a).
+template <typename S, typename T>
+__device__ __forceinline__ void pull(const S* __restrict__ src, int N, int nx, int xm, int xc, int xp, int ym,
+                                     int yc, int yp, T f[9]) {
+    f[0] = (T)src[0 * N + yc * nx + xc];
+    f[1] = (T)src[1 * N + yc * nx + xm];
+    f[2] = (T)src[2 * N + ym * nx + xc];
+    f[3] = (T)src[3 * N + yc * nx + xp];
+    f[4] = (T)src[4 * N + yp * nx + xc];
+    f[5] = (T)src[5 * N + ym * nx + xm];
+    f[6] = (T)src[6 * N + ym * nx + xp];
+    f[7] = (T)src[7 * N + yp * nx + xp];
+    f[8] = (T)src[8 * N + yp * nx + xm];
+}
+
+template <typename T>
+__device__ __forceinline__ T sum9(const T f[9]) {
+    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+template <typename T>
+__device__ __forceinline__ T jx9(const T f[9]) { return (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]); }
+template <typename T>
+__device__ __forceinline__ T jy9(const T f[9]) { return (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]); }
+
+// Isotropic stencils on an LDS plane of row width W (y + 1 is +W).
+//   lap  = [4 (E + W + N + S) + (NE + NW + SW + SE) - 20 c] / 6
+//   d/dx = [4 (E - W) + (NE - NW - SW + SE)] / 12          (Eq. 17)
+//   d/dy = [4 (N - S) + (NE + NW - SW - SE)] / 12
+template <int W, typename T>
+__device__ __forceinline__ T lap(const T* s, int c) {
+    const T ax = (s[c + 1] + s[c - 1]) + (s[c + W] + s[c - W]);
+    const T dg = (s[c + W + 1] + s[c + W - 1]) + (s[c - W - 1] + s[c - W + 1]);
+    return (T(4) * ax + dg - T(20) * s[c]) * T(1.0 / 6.0);
+}
+template <int W, typename T>
+__device__ __forceinline__ T ddx(const T* s, int c) {
+    return (T(4) * (s[c + 1] - s[c - 1]) + ((s[c + W + 1] - s[c + W - 1]) + (s[c - W + 1] - s[c - W - 1]))) *
+           T(1.0 / 12.0);
+}
+template <int W, typename T>
+__device__ __forceinline__ T ddy(const T* s, int c) {
+    return (T(4) * (s[c + W] - s[c - W]) + ((s[c + W + 1] + s[c + W - 1]) - (s[c - W - 1] + s[c - W + 1]))) *
+           T(1.0 / 12.0);
+}
+
+// BGK collision with Guo forcing (Eq. 14) and, for the improved scheme, the
+// correction term C of Eqs. 28-29 in population form; f holds the incoming
+// populations minus fbar and receives f* minus fbar.
+//   drho = rho - rho_ref, dpm = p_m - pm_ref (standard: drho / 3),
+//   php = p_m - rho/3 (zero in the standard scheme), Cxx = 3 d_x, Cyy = 3 d_y.
+// Equilibrium minus reference (M^-1 of Eq. 27 / Eq. 11):
+//   rest: drho - 5 dpm / 3 - (2/3) rho u^2
+//   axis: dpm / 3  + rho/9  (3 eu + 4.5 eu^2 - 1.5 u^2) - php eu / 2
+//   diag: dpm / 12 + rho/36 (3 eu + 4.5 eu^2 - 1.5 u^2) + php eu / 4
+template <typename T>
+__device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
+                                        T Cyy, T omega) {
+    const T usq = ux * ux + uy * uy;
+    const T uF = ux * Fx + uy * Fy;
+    const T om2 = T(1) - T(0.5) * omega;
+    const T r9 = rho * T(1.0 / 9.0), r36 = rho * T(1.0 / 36.0);
+    const T Ca = (Cxx - T(2) * Cyy) * T(1.0 / 6.0);   // +-x
+    const T Cb = (Cyy - T(2) * Cxx) * T(1.0 / 6.0);   // +-y
+    const T Cd = (Cxx + Cyy) * T(1.0 / 6.0);          // diagonals
+    const T Cr = -T(2) * Cd;                          // rest
+    {
+        const T feq = drho - T(5.0 / 3.0) * dpm - T(2.0 / 3.0) * rho * usq;
+        const T G = T(4.0 / 9.0) * (T(-3) * uF);
+        f[0] = f[0] - omega * (f[0] - feq) + om2 * (G + Cr);
+    }
+    const T ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
+    const T ud = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+#define LBM_AXIS(a, EX, EY, CC)                                                             \
+    {                                                                                       \
+        const T eu = T(EX) * ux + T(EY) * uy;                                               \
+        const T eF = T(EX) * Fx + T(EY) * Fy;                                               \
+        const T feq = ua + r9 * (T(3) * eu + T(4.5) * eu * eu) - T(0.5) * php * eu;         \
+        const T G = T(1.0 / 9.0) * (T(3) * (eF - uF) + T(9) * eu * eF);                     \
+        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + CC);                                \
+    }
+#define LBM_DIAG(a, EX, EY)                                                                 \
+    {                                                                                       \
+        const T eu = T(EX) * ux + T(EY) * uy;                                               \
+        const T eF = T(EX) * Fx + T(EY) * Fy;                                               \
+        const T feq = ud + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;       \
+        const T G = T(1.0 / 36.0) * (T(3) * (eF - uF) + T(9) * eu * eF);                    \
+        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + Cd);                                \
+    }
+    LBM_AXIS(1, 1, 0, Ca)
+    LBM_AXIS(2, 0, 1, Cb)
+    LBM_AXIS(3, -1, 0, Ca)
+    LBM_AXIS(4, 0, -1, Cb)
+    LBM_DIAG(5, 1, 1)
+    LBM_DIAG(6, -1, 1)
+    LBM_DIAG(7, -1, -1)
+    LBM_DIAG(8, 1, -1)
+#undef LBM_AXIS
+#undef LBM_DIAG
+}
+
+// Equilibrium minus reference for initialisation (same closed forms, no force).
+template <typename T>
+__device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy, T dpm, T php) {
+    const T usq = ux * ux + uy * uy;
+    const T r9 = rho * T(1.0 / 9.0), r36 = rho * T(1.0 / 36.0);
+    feq[0] = drho - T(5.0 / 3.0) * dpm - T(2.0 / 3.0) * rho * usq;
+    const T ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
+    const T ud = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const T eu = T(ex[a]) * ux + T(ey[a]) * uy;
+        if (a < 5)
+            feq[a] = ua + r9 * (T(3) * eu + T(4.5) * eu * eu) - T(0.5) * php * eu;
+        else
+            feq[a] = ud + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused step.  Stages on one tile of BX x BY output nodes:
+//   A  rho (and j) on the tile + 3 halo rings, from pulled populations
+//   B  mu = mu_EOS(rho) - kappa lap(rho) on tile + 2 (Eq. 2); P on tile + 2 (P-tensor form)
+//   C  F (Eq. 13 / Eq. 24), u = (j + F/2)/rho (Eq. 12), psi = phi u (Eq. 29) on tile + 1
+//   D  collision (Eq. 9 / Eq. 28 with Lambda = I/tau) and store, or field output
+// FIELDS = true writes rho, u, mu of the current time level instead of colliding.
+template <typename S, typename T, int V, int BX, int BY, bool FIELDS>
+__global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
+    constexpr int NT = BX * BY;
+    constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
+    constexpr bool IMP = (V == kImproved);
+    constexpr bool PT = (V == kStdPtensor);
+    __shared__ T s_rho[H3 * W3];
+    __shared__ T s_mu[H2 * W2];
+    __shared__ T s_a[H1 * W1];            // j_x, then psi_x = phi u_x
+    __shared__ T s_b[H1 * W1];            // j_y, then psi_y
+    __shared__ T s_F[2 * NT], s_u[2 * NT];
+    __shared__ T s_P[PT ? 3 * H2 * W2 : 1];
+    __shared__ double s_red[7 * (NT / 64)];
+    __shared__ unsigned s_ured[NT / 64];
+
+    const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
+    if (t_idx >= args.ntiles) return;
+    const Tile tile = args.tiles[t_idx];
+    const LatticeRec& R = args.recs[tile.lat];
+    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
+    // this one starts, so one thread reads it and the whole block follows.
+    __shared__ unsigned s_skip;
+    if (threadIdx.x == 0) s_skip = __atomic_load_n(args.status + tile.lat, __ATOMIC_RELAXED);
+    __syncthreads();
+    if (s_skip != 0u) return;
+
+    const int nx = R.nx, ny = R.ny, N = nx * ny;
+    const int sx = R.slow_x, sy = R.slow_y;
+    const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + R.state_offset * 9;
+    S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + R.state_offset * 9;
+    const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
+    const T kappa = (T)R.kappa, omega = (T)R.omega;
+    const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref;
+    const int x0 = tile.x0, y0 = tile.y0;
+    const int tid = threadIdx.x;
+    const int lx0 = tid % BX, ly0 = tid / BX;
+
+    // ---- stage A: interior node owned by this thread (kept in registers) ----
+    T fown[9];
+    {
+        const int gx = x0 + lx0, gy = y0 + ly0;
+        const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
+        const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, fown);
+        s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
+        s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
+        s_b[(ly0 + 1) * W1 + lx0 + 1] = jy9(fown);
+    }
+    // ---- stage A: the three halo rings ----
+    for (int k = tid; k < H3 * W3 - NT; k += NT) {
+        int lx, ly;
+        if (k < 3 * W3) {
+            ly = k / W3; lx = k % W3;
+        } else if (k < 6 * W3) {
+            const int k2 = k - 3 * W3;
+            ly = H3 - 3 + k2 / W3; lx = k2 % W3;
+        } else {
+            const int k3 = k - 6 * W3;
+            ly = 3 + k3 / 6;
+            const int c = k3 % 6;
+            lx = c < 3 ? c : W3 - 6 + c;
+        }
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
+        const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+        T f[9];
+        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, f);
+        s_rho[ly * W3 + lx] = rho_ref + sum9(f);
+        if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
+            s_a[(ly - 2) * W1 + lx - 2] = jx9(f);
+            s_b[(ly - 2) * W1 + lx - 2] = jy9(f);
+        }
+    }
+    __syncthreads();
+
+    // ---- stage B: chemical potential (and pressure tensor) on tile + 2 ----
+    for (int k = tid; k < H2 * W2; k += NT) {
+        const int lx = k % W2, ly = k / W2;
+        const int c = (ly + 1) * W3 + lx + 1;
+        const T r = s_rho[c];
+        const T L = lap<W3>(s_rho, c);
+        s_mu[k] = eos.mu(r) - kappa * L;
+        if constexpr (PT) {
+            const T gx = ddx<W3>(s_rho, c), gy = ddy<W3>(s_rho, c);
+            const T p = eos.p(r) - kappa * r * L - T(0.5) * kappa * (gx * gx + gy * gy);   // Eq. 4
+            s_P[k] = p + kappa * gx * gx;                                                 // Eq. 5
+            s_P[H2 * W2 + k] = kappa * gx * gy;
+            s_P[2 * H2 * W2 + k] = p + kappa * gy * gy;
+        }
+    }
+    __syncthreads();
+
+    // ---- stage C: force, velocity, psi on tile + 1 ----
+    for (int k = tid; k < H1 * W1; k += NT) {
+        const int lx = k % W1, ly = k / W1;
+        const int c2 = (ly + 1) * W2 + lx + 1;
+        const int c3 = (ly + 2) * W3 + lx + 2;
+        const T r = s_rho[c3];
+        T Fx, Fy;
+        if constexpr (IMP) {
+            const T g = T(1.0 / 3.0) - r;                                                 // Eq. 24
+            Fx = g * ddx<W2>(s_mu, c2);
+            Fy = g * ddy<W2>(s_mu, c2);
+        } else if constexpr (PT) {
+            const T* Pxx = s_P;
+            const T* Pxy = s_P + H2 * W2;
+            const T* Pyy = s_P + 2 * H2 * W2;
+            Fx = ddx<W3>(s_rho, c3) * T(1.0 / 3.0) - (ddx<W2>(Pxx, c2) + ddy<W2>(Pxy, c2));
+            Fy = ddy<W3>(s_rho, c3) * T(1.0 / 3.0) - (ddx<W2>(Pxy, c2) + ddy<W2>(Pyy, c2));
+        } else {
+            Fx = ddx<W3>(s_rho, c3) * T(1.0 / 3.0) - r * ddx<W2>(s_mu, c2);
+            Fy = ddy<W3>(s_rho, c3) * T(1.0 / 3.0) - r * ddy<W2>(s_mu, c2);
+        }
+        const T ir = T(1) / r;
+        const T ux = (s_a[k] + T(0.5) * Fx) * ir;
+        const T uy = (s_b[k] + T(0.5) * Fy) * ir;
+        if constexpr (IMP) {
+            const T phi = r * T(1.0 / 3.0) - (T(1) + s_mu[c2]) * T(1.0 / 3.0);           // Eq. 29
+            s_a[k] = phi * ux;
+            s_b[k] = phi * uy;
+        }
+        if (lx >= 1 && lx <= BX && ly >= 1 && ly <= BY) {
+            const int i0 = (ly - 1) * BX + lx - 1;
+            s_F[i0] = Fx; s_F[NT + i0] = Fy;
+            s_u[i0] = ux; s_u[NT + i0] = uy;
+        }
+    }
+    __syncthreads();
+
+    // ---- stage D: collide and store (or write fields) ----
+    DiagAcc acc;
+    const int gx = x0 + lx0, gy = y0 + ly0;
+    if (gx < nx && gy < ny) {
+        const int c3 = (ly0 + 3) * W3 + lx0 + 3, c2 = (ly0 + 2) * W2 + lx0 + 2, c1 = (ly0 + 1) * W1 + lx0 + 1;
+        const T r = s_rho[c3];
+        const T mu = s_mu[c2];
+        const T Fx = s_F[tid], Fy = s_F[NT + tid], ux = s_u[tid], uy = s_u[NT + tid];
+        const T drho = sum9(fown);
+        const int node = gy * nx + gx;
+        if constexpr (FIELDS) {
+            const long long o = R.field_offset + node;
+            if (args.rho_out) args.rho_out[o] = (double)r;
+            if (args.mu_out) args.mu_out[o] = (double)mu;
+            if (args.u_out) {
+                args.u_out[o] = (double)ux;
+                args.u_out[args.field_total + o] = (double)uy;
+            }
+        } else {
+            T dpm, php, Cxx = T(0), Cyy = T(0);
+            if constexpr (IMP) {
+                const T pm = (T(1) + mu) * T(1.0 / 3.0);
+                dpm = (mu - mu_ref) * T(1.0 / 3.0);
+                php = pm - r * T(1.0 / 3.0);
+                Cxx = T(3) * ddx<W1>(s_a, c1);
+                Cyy = T(3) * ddy<W1>(s_b, c1);
+            } else {
+                dpm = drho * T(1.0 / 3.0);
+                php = T(0);
+            }
+            collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) dst[a * N + node] = (S)fown[a];
+        }
+        (void)pm_ref;
+        acc.mass = (double)drho;
+        acc.mx = (double)(r * ux);
+        acc.my = (double)(r * uy);
+        acc.umax2 = (double)(ux * ux + uy * uy);
+        acc.mumin = (double)mu;
+        acc.mumax = (double)mu;
+        acc.status = blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
+    }
+    block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+    if (threadIdx.x == 0 && args.partial[t_idx].status != 0u) atomicOr(args.status + tile.lat, args.partial[t_idx].status);
+}
+
+// Initialisation: f(x, 0) = f_eq(rho0, u0) (minus fbar), written where a pull
+// finds it: state[a][x - e_a].  One thread per node of all lattices.
+template <typename S, typename T, int V>
+__global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                            long long field_total) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int L = 0;
+    while (L + 1 < nlat && gid >= recs[L + 1].field_offset) ++L;
+    const LatticeRec& R = recs[L];
+    const long long local = gid - R.field_offset;
+    if (local < 0 || local >= R.nnodes) return;
+    const int nx = R.nx, ny = R.ny, N = nx * ny;
+    const int x = (int)(local % nx), y = (int)(local / nx);
+    const double* r0 = rho0 + R.field_offset;
+    auto at = [&](int dx, int dy) {
+        const int xx = ((x + dx) % nx + nx) % nx, yy = ((y + dy) % ny + ny) % ny;
+        return (T)r0[yy * nx + xx];
+    };
+    const T r = at(0, 0);
+    T ux = T(0), uy = T(0);
+    if (u0) {
+        ux = (T)u0[R.field_offset + local];
+        uy = (T)u0[field_total + R.field_offset + local];
+    }
+    T dpm, php;
+    if (V == kImproved) {
+        const T ax = (at(1, 0) + at(-1, 0)) + (at(0, 1) + at(0, -1));
+        const T dg = (at(1, 1) + at(-1, 1)) + (at(-1, -1) + at(1, -1));
+        const T L2 = (T(4) * ax + dg - T(20) * r) * T(1.0 / 6.0);
+        const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
+        const T mu = eos.mu(r) - (T)R.kappa * L2;
+        dpm = (mu - (T)R.mu_ref) * T(1.0 / 3.0);
+        php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+    } else {
+        dpm = (r - (T)R.rho_ref) * T(1.0 / 3.0);
+        php = T(0);
+    }
+    T feq[9];
+    equilibrium<T>(feq, r, r - (T)R.rho_ref, ux, uy, dpm, php);
+    S* st = state + R.state_offset * 9;
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const int sx = ((x - ex[a]) % nx + nx) % nx, sy = ((y - ey[a]) % ny + ny) % ny;
+        st[a * N + sy * nx + sx] = (S)feq[a];
+    }
+}
+
+// Post-streaming populations f_a(x, t) as float64 (fbar added back), or the reverse.
+template <typename S, bool GET>
+__global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, double* f, long long field_total) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int L = 0;
+    while (L + 1 < nlat && gid >= recs[L + 1].field_offset) ++L;
+    const LatticeRec& R = recs[L];
+    const long long local = gid - R.field_offset;
+    if (local < 0 || local >= R.nnodes) return;
+    const int nx = R.nx, ny = R.ny, N = nx * ny;
+    const int x = (int)(local % nx), y = (int)(local / nx);
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    S* st = state + R.state_offset * 9;
+    for (int a = 0; a < 9; ++a) {
+        const int sx = ((x - ex[a]) % nx + nx) % nx, sy = ((y - ey[a]) % ny + ny) % ny;
+        const long long fo = (long long)a * field_total + R.field_offset + local;
+        if (GET)
+            f[fo] = (double)st[a * N + sy * nx + sx] + R.fbar[a];
+        else
+            st[a * N + sy * nx + sx] = (S)(f[fo] - R.fbar[a]);
+    }
+}
+
+}  // namespace d2q9
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called by the runtime).
+
+namespace {
+template <typename S, typename T, int V, int BX, int BY>
+hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, bool fields) {
+    if (fields)
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename S, typename T, int V>
+hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, bool fields, int shape) {
+    switch (shape) {
+        case 0: return launch_step_t<S, T, V, 32, 8>(a, grid, s, fields);
+        case 1: return launch_step_t<S, T, V, 64, 4>(a, grid, s, fields);
+        case 2: return launch_step_t<S, T, V, 32, 16>(a, grid, s, fields);
+        case 3: return launch_step_t<S, T, V, 16, 16>(a, grid, s, fields);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+extern const int kD2Q9Shapes[][2];
+const int kD2Q9Shapes[][2] = {{32, 8}, {64, 4}, {32, 16}, {16, 16}};
+extern const int kNumD2Q9Shapes;
+const int kNumD2Q9Shapes = 4;
+
+hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
+                            bool fields) {
+    if (precision == 0) {
+        switch (variant) {
+            case kStdChempot: return launch_shape<double, double, kStdChempot>(a, grid, s, fields, shape);
+            case kStdPtensor: return launch_shape<double, double, kStdPtensor>(a, grid, s, fields, shape);
+            case kImproved: return launch_shape<double, double, kImproved>(a, grid, s, fields, shape);
+        }
+    } else {
+        switch (variant) {
+            case kStdChempot: return launch_shape<float, float, kStdChempot>(a, grid, s, fields, shape);
+            case kStdPtensor: return launch_shape<float, float, kStdPtensor>(a, grid, s, fields, shape);
+            case kImproved: return launch_shape<float, float, kImproved>(a, grid, s, fields, shape);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t d2q9_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                            long long total, hipStream_t s, int precision, int variant) {
+    const int B = 256;
+    const int grid = (int)((total + B - 1) / B);
+    if (grid == 0) return hipSuccess;
+    const bool imp = variant == kImproved;
+    if (precision == 0) {
+        if (imp)
+            hipLaunchKernelGGL((d2q9::init_kernel<double, double, kImproved>), dim3(grid), dim3(B), 0, s,
+                               (double*)state, recs, nlat, rho0, u0, total);
+        else
+            hipLaunchKernelGGL((d2q9::init_kernel<double, double, kStdChempot>), dim3(grid), dim3(B), 0, s,
+                               (double*)state, recs, nlat, rho0, u0, total);
+    } else {
+        if (imp)
+            hipLaunchKernelGGL((d2q9::init_kernel<float, float, kImproved>), dim3(grid), dim3(B), 0, s,
+                               (float*)state, recs, nlat, rho0, u0, total);
+        else
+            hipLaunchKernelGGL((d2q9::init_kernel<float, float, kStdChempot>), dim3(grid), dim3(B), 0, s,
+                               (float*)state, recs, nlat, rho0, u0, total);
+    }
+    return hipGetLastError();
+}
+
+hipError_t d2q9_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
+                               hipStream_t s, int precision, bool get) {
+    const int B = 256;
+    const int grid = (int)((total + B - 1) / B);
+    if (grid == 0) return hipSuccess;
+    if (precision == 0) {
+        if (get)
+            hipLaunchKernelGGL((d2q9::convert_kernel<double, true>), dim3(grid), dim3(B), 0, s, (double*)state,
+                               recs, nlat, f, total);
+        else
+            hipLaunchKernelGGL((d2q9::convert_kernel<double, false>), dim3(grid), dim3(B), 0, s, (double*)state,
+                               recs, nlat, f, total);
+    } else {
+        if (get)
+            hipLaunchKernelGGL((d2q9::convert_kernel<float, true>), dim3(grid), dim3(B), 0, s, (float*)state,
+                               recs, nlat, f, total);
+        else
+            hipLaunchKernelGGL((d2q9::convert_kernel<float, false>), dim3(grid), dim3(B), 0, s, (float*)state,
+                               recs, nlat, f, total);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

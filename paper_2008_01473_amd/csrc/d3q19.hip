@@ -1,0 +1,620 @@
+// D3Q19 kernels: the fused time step as a 2.5D sweep (one work group per
+// BX x BY column of output nodes and a chunk of z-slices, rings of slices in
+// LDS), the initialisation from (rho0, u0), and conversion of the stored state
+// to and from post-streaming populations.
+//
+// Velocity order: 0 rest; 1 +x; 2 -x; 3 +y; 4 -y; 5 +z; 6 -z;
+//   7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1) 12 (-1,0,-1)
+//   13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1).
+// State layout and pull convention as in the D2Q9 kernels: population a of a
+// lattice at state_offset*19 + a*nnodes + (z*ny + y)*nx + x holds f*_a(x) of the
+// previous step; a step reads f_a(x) = f*_a(x - e_a) (Eq. 10).
+//
+// The D3Q19 forms of the improved equilibrium and of the correction term are
+// the paper's D2Q9 constructions carried to 19 velocities by the same rules:
+// second moments p_m I + rho u u (Eq. 25), third moments of Eq. 26, fourth
+// moments shifted by (p_m - rho/3)/3 as Eq. 27 does on D2Q9; C with zero mass
+// and momentum, second moments diag(3 d_i) and no higher orthogonal moments.
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+#include "lbm_shared.hpp"
+
+namespace lbm {
+namespace d3q19 {
+
+__device__ constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// Pull the 19 populations arriving at a node; X[k], Y[k], Z[k] (k = 0,1,2 for
+// offsets -1, 0, +1) are the wrapped x index, y*nx and z*nx*ny of the node's
+// neighbourhood.  Source of population a is x - e_a.
+template <typename S, typename T>
+__device__ __forceinline__ void pull(const S* __restrict__ src, int N, const int X[3], const int Y[3],
+                                     const int Z[3], T f[19]) {
+#pragma unroll
+    for (int a = 0; a < 19; ++a) f[a] = (T)src[a * N + Z[1 - EZ[a]] + Y[1 - EY[a]] + X[1 - EX[a]]];
+}
+
+template <typename T>
+__device__ __forceinline__ T sum19(const T f[19]) {
+    T s0 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
+    T s1 = (f[7] + f[8]) + (f[9] + f[10]) + (f[11] + f[12]);
+    T s2 = (f[13] + f[14]) + (f[15] + f[16]) + (f[17] + f[18]);
+    return s0 + (s1 + s2);
+}
+template <typename T>
+__device__ __forceinline__ void mom19(const T f[19], T& jx, T& jy, T& jz) {
+    jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
+    jy = (f[3] - f[4]) + (f[7] - f[8]) + (f[10] - f[9]) + (f[15] - f[16]) + (f[17] - f[18]);
+    jz = (f[5] - f[6]) + (f[11] - f[12]) + (f[14] - f[13]) + (f[15] - f[16]) + (f[18] - f[17]);
+}
+
+// Isotropic stencils on three consecutive LDS slices (Dn = z-1, P = z, U = z+1)
+// of row width W:  grad = 3 sum_a w_a phi(x + e_a) e_a  (Eq. 17),
+// lap = 6 sum_a w_a [phi(x + e_a) - phi(x)] = (1/3) sum_axis + (1/6) sum_edge - 4 phi.
+template <int W, typename T>
+__device__ __forceinline__ T gx(const T* Dn, const T* P, const T* U, int c) {
+    return T(1.0 / 6.0) * (P[c + 1] - P[c - 1]) +
+           T(1.0 / 12.0) * ((P[c + W + 1] - P[c - W - 1]) + (P[c - W + 1] - P[c + W - 1]) +
+                            (U[c + 1] - Dn[c - 1]) + (Dn[c + 1] - U[c - 1]));
+}
+template <int W, typename T>
+__device__ __forceinline__ T gy(const T* Dn, const T* P, const T* U, int c) {
+    return T(1.0 / 6.0) * (P[c + W] - P[c - W]) +
+           T(1.0 / 12.0) * ((P[c + W + 1] - P[c - W - 1]) + (P[c + W - 1] - P[c - W + 1]) +
+                            (U[c + W] - Dn[c - W]) + (Dn[c + W] - U[c - W]));
+}
+template <int W, typename T>
+__device__ __forceinline__ T gz(const T* Dn, const T* P, const T* U, int c) {
+    return T(1.0 / 6.0) * (U[c] - Dn[c]) +
+           T(1.0 / 12.0) * ((U[c + 1] - Dn[c - 1]) + (U[c - 1] - Dn[c + 1]) + (U[c + W] - Dn[c - W]) +
+                            (U[c - W] - Dn[c + W]));
+}
+template <int W, typename T>
+__device__ __forceinline__ T lap(const T* Dn, const T* P, const T* U, int c) {
+    const T ax = (P[c + 1] + P[c - 1]) + (P[c + W] + P[c - W]) + (U[c] + Dn[c]);
+    const T ed = (P[c + W + 1] + P[c + W - 1]) + (P[c - W + 1] + P[c - W - 1]) + (U[c + 1] + U[c - 1]) +
+                 (U[c + W] + U[c - W]) + (Dn[c + 1] + Dn[c - 1]) + (Dn[c + W] + Dn[c - W]);
+    return T(1.0 / 3.0) * ax + T(1.0 / 6.0) * ed - T(4) * P[c];
+}
+
+// The same gradient with an accessor v(dx, dy, dz) giving the field at x + (dx, dy, dz).
+template <typename T, class F>
+__device__ __forceinline__ T agx(F v) {
+    return T(1.0 / 6.0) * (v(1, 0, 0) - v(-1, 0, 0)) +
+           T(1.0 / 12.0) * ((v(1, 1, 0) - v(-1, -1, 0)) + (v(1, -1, 0) - v(-1, 1, 0)) + (v(1, 0, 1) - v(-1, 0, -1)) +
+                            (v(1, 0, -1) - v(-1, 0, 1)));
+}
+template <typename T, class F>
+__device__ __forceinline__ T agy(F v) {
+    return T(1.0 / 6.0) * (v(0, 1, 0) - v(0, -1, 0)) +
+           T(1.0 / 12.0) * ((v(1, 1, 0) - v(-1, -1, 0)) + (v(-1, 1, 0) - v(1, -1, 0)) + (v(0, 1, 1) - v(0, -1, -1)) +
+                            (v(0, 1, -1) - v(0, -1, 1)));
+}
+template <typename T, class F>
+__device__ __forceinline__ T agz(F v) {
+    return T(1.0 / 6.0) * (v(0, 0, 1) - v(0, 0, -1)) +
+           T(1.0 / 12.0) * ((v(1, 0, 1) - v(-1, 0, -1)) + (v(-1, 0, 1) - v(1, 0, -1)) + (v(0, 1, 1) - v(0, -1, -1)) +
+                            (v(0, -1, 1) - v(0, 1, -1)));
+}
+
+// BGK collision with Guo forcing and the correction term (improved scheme);
+// f holds populations minus fbar on entry and f* minus fbar on exit.
+// Equilibrium minus reference:
+//   rest: drho - 2 dpm - rho u^2 / 2
+//   axis: dpm / 6  + rho/18 (3 eu + 4.5 eu^2 - 1.5 u^2) - php eu
+//   edge: dpm / 12 + rho/36 (3 eu + 4.5 eu^2 - 1.5 u^2) + php eu / 4
+// Correction (C_ii = 3 d_i, S = C_xx + C_yy + C_zz):
+//   rest -5S/21; +-i (C_ii - 6 (S - C_ii))/42; ij-edges (5 C_ii + 5 C_jj - 2 C_kk)/42.
+template <typename T>
+__device__ __forceinline__ void collide(T f[19], T rho, T drho, T ux, T uy, T uz, T Fx, T Fy, T Fz, T dpm,
+                                        T php, T Cxx, T Cyy, T Czz, T omega) {
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T om2 = T(1) - T(0.5) * omega;
+    const T r18 = rho * T(1.0 / 18.0), r36 = rho * T(1.0 / 36.0);
+    const T S = Cxx + Cyy + Czz;
+    const T k42 = T(1.0 / 42.0);
+    const T Cax[3] = {(T(7) * Cxx - T(6) * S) * k42, (T(7) * Cyy - T(6) * S) * k42, (T(7) * Czz - T(6) * S) * k42};
+    const T Cxy = (T(7) * (Cxx + Cyy) - T(2) * S) * k42;
+    const T Cxz = (T(7) * (Cxx + Czz) - T(2) * S) * k42;
+    const T Cyz = (T(7) * (Cyy + Czz) - T(2) * S) * k42;
+    {
+        const T feq = drho - T(2) * dpm - T(0.5) * rho * usq;
+        const T G = T(1.0 / 3.0) * (T(-3) * uF);
+        f[0] = f[0] - omega * (f[0] - feq) + om2 * (G + T(-5.0 / 21.0) * S);
+    }
+    const T ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
+    const T ue = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        const T ex = T(EX[a]), ey = T(EY[a]), ez = T(EZ[a]);
+        const T eu = ex * ux + ey * uy + ez * uz;
+        const T eF = ex * Fx + ey * Fy + ez * Fz;
+        T feq, G, C;
+        if (a < 7) {
+            feq = ua + r18 * (T(3) * eu + T(4.5) * eu * eu) - php * eu;
+            G = T(1.0 / 18.0) * (T(3) * (eF - uF) + T(9) * eu * eF);
+            C = Cax[(a - 1) >> 1];
+        } else {
+            feq = ue + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;
+            G = T(1.0 / 36.0) * (T(3) * (eF - uF) + T(9) * eu * eF);
+            C = (a < 11) ? Cxy : ((a < 15) ? Cxz : Cyz);
+        }
+        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + C);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void equilibrium(T feq[19], T rho, T drho, T ux, T uy, T uz, T dpm, T php) {
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const T r18 = rho * T(1.0 / 18.0), r36 = rho * T(1.0 / 36.0);
+    feq[0] = drho - T(2) * dpm - T(0.5) * rho * usq;
+    const T ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
+    const T ue = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+        const T eu = T(EX[a]) * ux + T(EY[a]) * uy + T(EZ[a]) * uz;
+        feq[a] = (a < 7) ? ua + r18 * (T(3) * eu + T(4.5) * eu * eu) - php * eu
+                         : ue + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused step as a sweep over z.  Iteration `it` handles slice za = z0 - 3 + it:
+//   A  pull populations of slice za, rho on tile + 3 rings, j on tile + 1
+//   B  mu (and P) of slice za - 1 on tile + 2
+//   C  F and u (and psi = phi u, improved) of slice za - 2
+//   D  collide and store slice za - 3 (the thread's own populations, pulled
+//      three iterations earlier, wait in a register FIFO when FIFO is set)
+// Rings hold 4 slices (slot = (z - z0 + 8) & 3); F and u of the tile hold 2.
+template <typename S, typename T, int V, int BX, int BY, bool FIELDS>
+__global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
+    constexpr int NT = BX * BY;
+    constexpr int W3 = BX + 6, H3 = BY + 6, A3 = W3 * H3;
+    constexpr int W2 = BX + 4, H2 = BY + 4, A2 = W2 * H2;
+    constexpr int W1 = BX + 2, H1 = BY + 2, A1 = W1 * H1;
+    constexpr bool IMP = (V == kImproved);
+    constexpr bool PT = (V == kStdPtensor);
+    constexpr bool FIFO = sizeof(T) == 4;       // float64 re-reads its populations in stage D instead
+    __shared__ T s_rho[4 * A3];
+    __shared__ T s_mu[4 * A2];
+    __shared__ T s_j[3 * 4 * A1];
+    __shared__ T s_psi[IMP ? 3 * 4 * A1 : 1];
+    __shared__ T s_P[PT ? 4 * 3 * A2 : 1];      // p, d_x rho, d_y rho, d_z rho; ring of 3 slices
+    __shared__ T s_fu[6 * 2 * NT];              // Fx Fy Fz ux uy uz of the tile, 2 slices
+    __shared__ double s_red[7 * (NT / 64)];
+    __shared__ unsigned s_ured[NT / 64];
+
+    const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
+    if (t_idx >= args.ntiles) return;
+    const Tile tile = args.tiles[t_idx];
+    const LatticeRec& R = args.recs[tile.lat];
+    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
+    // this one starts, so one thread reads it and the whole block follows.
+    __shared__ unsigned s_skip;
+    if (threadIdx.x == 0) s_skip = __atomic_load_n(args.status + tile.lat, __ATOMIC_RELAXED);
+    __syncthreads();
+    if (s_skip != 0u) return;
+
+    const int nx = R.nx, ny = R.ny, nz = R.nz;
+    const int N = nx * ny * nz, NXY = nx * ny;
+    const int sx = R.slow_x, sy = R.slow_y, sz = R.slow_z;
+    const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + R.state_offset * 19;
+    S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + R.state_offset * 19;
+    const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
+    const T kappa = (T)R.kappa, omega = (T)R.omega;
+    const T rho_ref = (T)R.rho_ref, mu_ref = (T)R.mu_ref;
+    const int x0 = tile.x0, y0 = tile.y0, z0 = tile.z0, zn = tile.zn;
+    const int tid = threadIdx.x;
+    const int lx0 = tid % BX, ly0 = tid / BX;
+    const int gx0 = x0 + lx0, gy0 = y0 + ly0;
+    const bool own_valid = gx0 < nx && gy0 < ny;
+
+    // wrapped x and y of the owned column and its neighbours (fixed over the sweep)
+    int OX[3], OY[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        OX[k] = wrap(gx0 - 1 + k, nx, sx);
+        OY[k] = wrap(gy0 - 1 + k, ny, sy) * nx;
+    }
+
+    T fifo[FIFO ? 4 : 1][19];
+    DiagAcc acc;
+
+    for (int it = 0; it < zn + 6; ++it) {
+        const int za = z0 - 3 + it;
+        int Z[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Z[k] = wrap(za - 1 + k, nz, sz) * NXY;
+        const int slA = (za - z0 + 8) & 3;
+
+        // ---- A: interior column of this thread ----
+        {
+            T f[19];
+            pull<S, T>(src, N, OX, OY, Z, f);
+            s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum19(f);
+            T jx, jy, jz;
+            mom19(f, jx, jy, jz);
+            const int c1 = slA * A1 + (ly0 + 1) * W1 + lx0 + 1;
+            s_j[c1] = jx; s_j[4 * A1 + c1] = jy; s_j[8 * A1 + c1] = jz;
+            if constexpr (FIFO) {
+#pragma unroll
+                for (int a = 0; a < 19; ++a) fifo[3][a] = f[a];
+            }
+        }
+        // ---- A: halo rings of the slice ----
+        for (int k = tid; k < A3 - NT; k += NT) {
+            int lx, ly;
+            if (k < 3 * W3) {
+                ly = k / W3; lx = k % W3;
+            } else if (k < 6 * W3) {
+                const int k2 = k - 3 * W3;
+                ly = H3 - 3 + k2 / W3; lx = k2 % W3;
+            } else {
+                const int k3 = k - 6 * W3;
+                ly = 3 + k3 / 6;
+                const int c = k3 % 6;
+                lx = c < 3 ? c : W3 - 6 + c;
+            }
+            const int hx = x0 - 3 + lx, hy = y0 - 3 + ly;
+            int X[3], Y[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                X[q] = wrap(hx - 1 + q, nx, sx);
+                Y[q] = wrap(hy - 1 + q, ny, sy) * nx;
+            }
+            T f[19];
+            pull<S, T>(src, N, X, Y, Z, f);
+            s_rho[slA * A3 + ly * W3 + lx] = rho_ref + sum19(f);
+            if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
+                T jx, jy, jz;
+                mom19(f, jx, jy, jz);
+                const int c1 = slA * A1 + (ly - 2) * W1 + lx - 2;
+                s_j[c1] = jx; s_j[4 * A1 + c1] = jy; s_j[8 * A1 + c1] = jz;
+            }
+        }
+        __syncthreads();
+
+        // ---- B: mu (and P) of slice za - 1 on tile + 2 ----
+        if (it >= 2) {
+            const int zb = za - 1;
+            const T* Rd = s_rho + ((zb - 1 - z0 + 8) & 3) * A3;
+            const T* Rp = s_rho + ((zb - z0 + 8) & 3) * A3;
+            const T* Ru = s_rho + ((zb + 1 - z0 + 8) & 3) * A3;
+            const int slB = (zb - z0 + 8) & 3;
+            for (int k = tid; k < A2; k += NT) {
+                const int lx = k % W2, ly = k / W2;
+                const int c = (ly + 1) * W3 + lx + 1;
+                const T r = Rp[c];
+                const T L = lap<W3>(Rd, Rp, Ru, c);
+                s_mu[slB * A2 + k] = eos.mu(r) - kappa * L;
+                if constexpr (PT) {
+                    const T g0 = gx<W3>(Rd, Rp, Ru, c), g1 = gy<W3>(Rd, Rp, Ru, c), g2 = gz<W3>(Rd, Rp, Ru, c);
+                    // Eq. 4; the tensor of Eq. 5 is rebuilt from (p, grad rho) where it is differentiated
+                    const T p = eos.p(r) - kappa * r * L - T(0.5) * kappa * (g0 * g0 + g1 * g1 + g2 * g2);
+                    T* P = s_P + ((zb - z0 + 9) % 3) * A2 + k;
+                    P[0] = p;
+                    P[3 * A2] = g0;
+                    P[6 * A2] = g1;
+                    P[9 * A2] = g2;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- C: F, u (and psi) of slice za - 2 ----
+        if (it >= 4) {
+            const int zc = za - 2;
+            const int sd = (zc - 1 - z0 + 8) & 3, sp = (zc - z0 + 8) & 3, su = (zc + 1 - z0 + 8) & 3;
+            const int sfu = (zc - z0 + 8) & 1;
+            constexpr int NC = IMP ? A1 : NT;          // improved needs psi on tile + 1
+            for (int k = tid; k < NC; k += NT) {
+                int lx, ly;     // tile + 1 coordinates
+                if (IMP) { lx = k % W1; ly = k / W1; } else { lx = k % BX + 1; ly = k / BX + 1; }
+                const int c2 = (ly + 1) * W2 + lx + 1;
+                const int c3 = (ly + 2) * W3 + lx + 2;
+                const T r = s_rho[sp * A3 + c3];
+                T Fx, Fy, Fz;
+                const T* Md = s_mu + sd * A2;
+                const T* Mp = s_mu + sp * A2;
+                const T* Mu = s_mu + su * A2;
+                if constexpr (IMP) {
+                    const T g = T(1.0 / 3.0) - r;                                       // Eq. 24
+                    Fx = g * gx<W2>(Md, Mp, Mu, c2);
+                    Fy = g * gy<W2>(Md, Mp, Mu, c2);
+                    Fz = g * gz<W2>(Md, Mp, Mu, c2);
+                } else {
+                    const T* Rd = s_rho + sd * A3;
+                    const T* Rp = s_rho + sp * A3;
+                    const T* Ru = s_rho + su * A3;
+                    const T ax = gx<W3>(Rd, Rp, Ru, c3) * T(1.0 / 3.0);
+                    const T ay = gy<W3>(Rd, Rp, Ru, c3) * T(1.0 / 3.0);
+                    const T az = gz<W3>(Rd, Rp, Ru, c3) * T(1.0 / 3.0);
+                    if constexpr (PT) {
+                        // P_ij = p delta_ij + kappa d_i rho d_j rho (Eq. 5); (div P)_j = sum_i d_i P_ij (Eq. 17)
+                        auto at = [&](int q, int dx, int dy, int dz) {
+                            return s_P[q * 3 * A2 + ((zc + dz - z0 + 9) % 3) * A2 + c2 + dy * W2 + dx];
+                        };
+                        auto Pf = [&](int i, int j) {
+                            return [&, i, j](int dx, int dy, int dz) {
+                                const T v = kappa * at(1 + i, dx, dy, dz) * at(1 + j, dx, dy, dz);
+                                return i == j ? v + at(0, dx, dy, dz) : v;
+                            };
+                        };
+                        const T dPx = agx<T>(Pf(0, 0)) + agy<T>(Pf(1, 0)) + agz<T>(Pf(2, 0));
+                        const T dPy = agx<T>(Pf(0, 1)) + agy<T>(Pf(1, 1)) + agz<T>(Pf(2, 1));
+                        const T dPz = agx<T>(Pf(0, 2)) + agy<T>(Pf(1, 2)) + agz<T>(Pf(2, 2));
+                        Fx = ax - dPx; Fy = ay - dPy; Fz = az - dPz;
+                    } else {
+                        Fx = ax - r * gx<W2>(Md, Mp, Mu, c2);
+                        Fy = ay - r * gy<W2>(Md, Mp, Mu, c2);
+                        Fz = az - r * gz<W2>(Md, Mp, Mu, c2);
+                    }
+                }
+                const int c1 = sp * A1 + ly * W1 + lx;
+                const T ir = T(1) / r;
+                const T ux = (s_j[c1] + T(0.5) * Fx) * ir;
+                const T uy = (s_j[4 * A1 + c1] + T(0.5) * Fy) * ir;
+                const T uz = (s_j[8 * A1 + c1] + T(0.5) * Fz) * ir;
+                if constexpr (IMP) {
+                    const T phi = r * T(1.0 / 3.0) - (T(1) + Mp[c2]) * T(1.0 / 3.0);    // Eq. 29
+                    s_psi[c1] = phi * ux;
+                    s_psi[4 * A1 + c1] = phi * uy;
+                    s_psi[8 * A1 + c1] = phi * uz;
+                }
+                if (lx >= 1 && lx <= BX && ly >= 1 && ly <= BY) {
+                    T* fu = s_fu + sfu * 6 * NT + (ly - 1) * BX + lx - 1;
+                    fu[0] = Fx; fu[NT] = Fy; fu[2 * NT] = Fz;
+                    fu[3 * NT] = ux; fu[4 * NT] = uy; fu[5 * NT] = uz;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- D: collide and store slice za - 3 ----
+        if (it >= 6 && own_valid) {
+            const int zd = za - 3;
+            const int sd = (zd - 1 - z0 + 8) & 3, sp = (zd - z0 + 8) & 3, su = (zd + 1 - z0 + 8) & 3;
+            const int sfu = (zd - z0 + 8) & 1;
+            const T r = s_rho[sp * A3 + (ly0 + 3) * W3 + lx0 + 3];
+            const T mu = s_mu[sp * A2 + (ly0 + 2) * W2 + lx0 + 2];
+            const T* fu = s_fu + sfu * 6 * NT + tid;
+            const T Fx = fu[0], Fy = fu[NT], Fz = fu[2 * NT], ux = fu[3 * NT], uy = fu[4 * NT], uz = fu[5 * NT];
+            T f[19];
+            if constexpr (FIFO) {
+#pragma unroll
+                for (int a = 0; a < 19; ++a) f[a] = fifo[0][a];
+            } else {
+                int Zd[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Zd[k] = wrap(zd - 1 + k, nz, sz) * NXY;
+                pull<S, T>(src, N, OX, OY, Zd, f);
+            }
+            const T drho = sum19(f);
+            const int node = zd * NXY + gy0 * nx + gx0;
+            if constexpr (FIELDS) {
+                const long long o = R.field_offset + node;
+                if (args.rho_out) args.rho_out[o] = (double)r;
+                if (args.mu_out) args.mu_out[o] = (double)mu;
+                if (args.u_out) {
+                    args.u_out[o] = (double)ux;
+                    args.u_out[args.field_total + o] = (double)uy;
+                    args.u_out[2 * args.field_total + o] = (double)uz;
+                }
+            } else {
+                T dpm, php, Cxx = T(0), Cyy = T(0), Czz = T(0);
+                if constexpr (IMP) {
+                    const int c1 = (ly0 + 1) * W1 + lx0 + 1;
+                    const T* Xd = s_psi + sd * A1; const T* Xp = s_psi + sp * A1; const T* Xu = s_psi + su * A1;
+                    const T* Yd = Xd + 4 * A1; const T* Yp = Xp + 4 * A1; const T* Yu = Xu + 4 * A1;
+                    const T* Zdd = Xd + 8 * A1; const T* Zp = Xp + 8 * A1; const T* Zu = Xu + 8 * A1;
+                    Cxx = T(3) * gx<W1>(Xd, Xp, Xu, c1);
+                    Cyy = T(3) * gy<W1>(Yd, Yp, Yu, c1);
+                    Czz = T(3) * gz<W1>(Zdd, Zp, Zu, c1);
+                    dpm = (mu - mu_ref) * T(1.0 / 3.0);
+                    php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+                } else {
+                    dpm = drho * T(1.0 / 3.0);
+                    php = T(0);
+                }
+                collide<T>(f, r, drho, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
+#pragma unroll
+                for (int a = 0; a < 19; ++a) dst[a * N + node] = (S)f[a];
+            }
+            acc.mass += (double)drho;
+            acc.mx += (double)(r * ux);
+            acc.my += (double)(r * uy);
+            acc.mz += (double)(r * uz);
+            acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy + uz * uz));
+            acc.mumin = fmin(acc.mumin, (double)mu);
+            acc.mumax = fmax(acc.mumax, (double)mu);
+            acc.status |= blowup_bits<T>(r, ux, uy, uz, R.rho_max);
+        }
+        if constexpr (FIFO) {
+#pragma unroll
+            for (int a = 0; a < 19; ++a) {
+                fifo[0][a] = fifo[1][a];
+                fifo[1][a] = fifo[2][a];
+                fifo[2][a] = fifo[3][a];
+            }
+        }
+        __syncthreads();
+    }
+    block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+    if (threadIdx.x == 0) {
+        const unsigned st = args.partial[t_idx].status;
+        if (st != 0u) atomicOr(args.status + tile.lat, st);
+    }
+}
+
+template <typename S, typename T, int V>
+__global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                            long long field_total) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int L = 0;
+    while (L + 1 < nlat && gid >= recs[L + 1].field_offset) ++L;
+    const LatticeRec& R = recs[L];
+    const long long local = gid - R.field_offset;
+    if (local < 0 || local >= R.nnodes) return;
+    const int nx = R.nx, ny = R.ny, nz = R.nz, NXY = nx * ny, N = NXY * nz;
+    const int x = (int)(local % nx), y = (int)((local / nx) % ny), z = (int)(local / NXY);
+    const double* r0 = rho0 + R.field_offset;
+    auto at = [&](int dx, int dy, int dz) {
+        const int xx = ((x + dx) % nx + nx) % nx, yy = ((y + dy) % ny + ny) % ny, zz = ((z + dz) % nz + nz) % nz;
+        return (T)r0[(zz * ny + yy) * nx + xx];
+    };
+    const T r = at(0, 0, 0);
+    T ux = T(0), uy = T(0), uz = T(0);
+    if (u0) {
+        ux = (T)u0[R.field_offset + local];
+        uy = (T)u0[field_total + R.field_offset + local];
+        uz = (T)u0[2 * field_total + R.field_offset + local];
+    }
+    T dpm, php;
+    if (V == kImproved) {
+        T ax = T(0), ed = T(0);
+#pragma unroll
+        for (int a = 1; a < 19; ++a) {
+            const T v = at(EX[a], EY[a], EZ[a]);
+            if (a < 7) ax += v; else ed += v;
+        }
+        const T L2 = T(1.0 / 3.0) * ax + T(1.0 / 6.0) * ed - T(4) * r;
+        const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
+        const T mu = eos.mu(r) - (T)R.kappa * L2;
+        dpm = (mu - (T)R.mu_ref) * T(1.0 / 3.0);
+        php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+    } else {
+        dpm = (r - (T)R.rho_ref) * T(1.0 / 3.0);
+        php = T(0);
+    }
+    T feq[19];
+    equilibrium<T>(feq, r, r - (T)R.rho_ref, ux, uy, uz, dpm, php);
+    S* st = state + R.state_offset * 19;
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+        const int sx = ((x - EX[a]) % nx + nx) % nx, sy = ((y - EY[a]) % ny + ny) % ny,
+                  sz = ((z - EZ[a]) % nz + nz) % nz;
+        st[a * N + (sz * ny + sy) * nx + sx] = (S)feq[a];
+    }
+}
+
+template <typename S, bool GET>
+__global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, double* f, long long field_total) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int L = 0;
+    while (L + 1 < nlat && gid >= recs[L + 1].field_offset) ++L;
+    const LatticeRec& R = recs[L];
+    const long long local = gid - R.field_offset;
+    if (local < 0 || local >= R.nnodes) return;
+    const int nx = R.nx, ny = R.ny, nz = R.nz, NXY = nx * ny, N = NXY * nz;
+    const int x = (int)(local % nx), y = (int)((local / nx) % ny), z = (int)(local / NXY);
+    S* st = state + R.state_offset * 19;
+    for (int a = 0; a < 19; ++a) {
+        const int sx = ((x - EX[a]) % nx + nx) % nx, sy = ((y - EY[a]) % ny + ny) % ny,
+                  sz = ((z - EZ[a]) % nz + nz) % nz;
+        const long long fo = (long long)a * field_total + R.field_offset + local;
+        const long long so = (long long)a * N + (sz * ny + sy) * nx + sx;
+        if (GET)
+            f[fo] = (double)st[so] + R.fbar[a];
+        else
+            st[so] = (S)(f[fo] - R.fbar[a]);
+    }
+}
+
+}  // namespace d3q19
+
+namespace {
+template <typename S, typename T, int V, int BX, int BY>
+hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, bool fields) {
+    if (fields)
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, s, a);
+    else
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, s, a);
+    return hipGetLastError();
+}
+template <typename S, typename T, int V>
+hipError_t launch3_shape(const StepArgs& a, int grid, hipStream_t s, bool fields, int shape) {
+    switch (shape) {
+        case 0: return launch3_t<S, T, V, 32, 8>(a, grid, s, fields);
+        case 1: return launch3_t<S, T, V, 16, 16>(a, grid, s, fields);
+        case 2: return launch3_t<S, T, V, 64, 4>(a, grid, s, fields);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+extern const int kD3Q19Shapes[][2];
+const int kD3Q19Shapes[][2] = {{32, 8}, {16, 16}, {64, 4}};
+extern const int kNumD3Q19Shapes;
+const int kNumD3Q19Shapes = 3;
+
+hipError_t d3q19_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
+                             bool fields) {
+    if (precision == 0) {
+        switch (variant) {
+            case kStdChempot: return launch3_shape<double, double, kStdChempot>(a, grid, s, fields, shape);
+            case kStdPtensor: return launch3_shape<double, double, kStdPtensor>(a, grid, s, fields, shape);
+            case kImproved: return launch3_shape<double, double, kImproved>(a, grid, s, fields, shape);
+        }
+    } else {
+        switch (variant) {
+            case kStdChempot: return launch3_shape<float, float, kStdChempot>(a, grid, s, fields, shape);
+            case kStdPtensor: return launch3_shape<float, float, kStdPtensor>(a, grid, s, fields, shape);
+            case kImproved: return launch3_shape<float, float, kImproved>(a, grid, s, fields, shape);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t d3q19_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
+                             long long total, hipStream_t s, int precision, int variant) {
+    const int B = 256;
+    const int grid = (int)((total + B - 1) / B);
+    if (grid == 0) return hipSuccess;
+    const bool imp = variant == kImproved;
+    if (precision == 0) {
+        if (imp)
+            hipLaunchKernelGGL((d3q19::init_kernel<double, double, kImproved>), dim3(grid), dim3(B), 0, s,
+                               (double*)state, recs, nlat, rho0, u0, total);
+        else
+            hipLaunchKernelGGL((d3q19::init_kernel<double, double, kStdChempot>), dim3(grid), dim3(B), 0, s,
+                               (double*)state, recs, nlat, rho0, u0, total);
+    } else {
+        if (imp)
+            hipLaunchKernelGGL((d3q19::init_kernel<float, float, kImproved>), dim3(grid), dim3(B), 0, s,
+                               (float*)state, recs, nlat, rho0, u0, total);
+        else
+            hipLaunchKernelGGL((d3q19::init_kernel<float, float, kStdChempot>), dim3(grid), dim3(B), 0, s,
+                               (float*)state, recs, nlat, rho0, u0, total);
+    }
+    return hipGetLastError();
+}
+
+hipError_t d3q19_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
+                                hipStream_t s, int precision, bool get) {
+    const int B = 256;
+    const int grid = (int)((total + B - 1) / B);
+    if (grid == 0) return hipSuccess;
+    if (precision == 0) {
+        if (get)
+            hipLaunchKernelGGL((d3q19::convert_kernel<double, true>), dim3(grid), dim3(B), 0, s, (double*)state,
+                               recs, nlat, f, total);
+        else
+            hipLaunchKernelGGL((d3q19::convert_kernel<double, false>), dim3(grid), dim3(B), 0, s, (double*)state,
+                               recs, nlat, f, total);
+    } else {
+        if (get)
+            hipLaunchKernelGGL((d3q19::convert_kernel<float, true>), dim3(grid), dim3(B), 0, s, (float*)state,
+                               recs, nlat, f, total);
+        else
+            hipLaunchKernelGGL((d3q19::convert_kernel<float, false>), dim3(grid), dim3(B), 0, s, (float*)state,
+                               recs, nlat, f, total);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

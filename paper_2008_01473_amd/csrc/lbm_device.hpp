@@ -1,0 +1,127 @@
+// Device helpers shared by the D2Q9 and D3Q19 kernels: periodic index wrap,
+// the bulk chemical potential / pressure of the two free energies, and the
+// block reduction of the per-tile diagnostics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_shared.hpp"
+
+namespace lbm {
+
+__device__ __forceinline__ float dev_log(float x) { return logf(x); }
+__device__ __forceinline__ double dev_log(double x) { return log(x); }
+__device__ __forceinline__ bool dev_finite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool dev_finite(double x) { return isfinite(x); }
+
+// Periodic wrap of a coordinate that is at most a few nodes outside [0, n).
+// `slow` is set by the host when n is too small for one conditional correction.
+__device__ __forceinline__ int wrap(int v, int n, int slow) {
+    if (slow) {
+        int r = v % n;
+        return r < 0 ? r + n : r;
+    }
+    v += (v < 0) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+
+// Bulk part of the chemical potential, mu_EOS = E_f'(rho), and p_EOS = rho E_f' - E_f.
+//   vdW (Eq. 30): E_f = rho R T ln[rho/(1 - b rho)] - a rho^2
+//   CS          : E_f = rho R T [ln rho + (4h - 3h^2)/(1 - h)^2] - a rho^2,  h = b rho / 4
+template <typename T>
+struct Eos {
+    int kind;
+    T a, b, RT;
+
+    __device__ __forceinline__ T mu(T rho) const {
+        if (kind == 0) {
+            const T ibr = T(1) / (T(1) - b * rho);
+            return RT * (dev_log(rho * ibr) + ibr) - T(2) * a * rho;
+        }
+        const T h = T(0.25) * b * rho;
+        const T iom = T(1) / (T(1) - h);
+        const T iom3 = iom * iom * iom;
+        return RT * (dev_log(rho) + T(1) + h * (T(8) - T(9) * h + T(3) * h * h) * iom3) - T(2) * a * rho;
+    }
+
+    __device__ __forceinline__ T p(T rho) const {
+        if (kind == 0) return rho * RT / (T(1) - b * rho) - a * rho * rho;
+        const T h = T(0.25) * b * rho;
+        const T iom = T(1) / (T(1) - h);
+        return rho * RT * (T(1) + h + h * h - h * h * h) * (iom * iom * iom) - a * rho * rho;
+    }
+};
+
+// Block -> tile mapping that keeps spatially adjacent tiles on one XCD: work
+// groups are dealt to the 8 XCDs round-robin, so block b runs on XCD b % 8 and
+// is given tile (b % 8) * tiles_per_xcd + b / 8 of the spatially ordered list.
+__device__ __forceinline__ int tile_of_block(int b, int tiles_per_xcd) {
+    return (b & 7) * tiles_per_xcd + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Per-thread diagnostics accumulator, reduced over the block in a fixed order.
+struct DiagAcc {
+    double mass = 0, mx = 0, my = 0, mz = 0, umax2 = 0;
+    double mumin = 1e300, mumax = -1e300;
+    unsigned status = 0;
+};
+
+template <int NT>
+__device__ __forceinline__ void block_reduce_store(const DiagAcc& a, DiagPartial* out, double* scratch,
+                                                   unsigned* uscratch) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
+                   wave_max(a.umax2), wave_min(a.mumin), wave_max(a.mumax)};
+    unsigned st = wave_or(a.status);
+    if (lane == 0) {
+        for (int k = 0; k < 7; ++k) scratch[k * NW + w] = v[k];
+        uscratch[w] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DiagPartial p;
+        p.mass = 0; p.momx = 0; p.momy = 0; p.momz = 0;
+        p.umax2 = 0; p.mumin = 1e300; p.mumax = -1e300; p.status = 0; p.pad = 0;
+        for (int i = 0; i < NW; ++i) {
+            p.mass += scratch[0 * NW + i];
+            p.momx += scratch[1 * NW + i];
+            p.momy += scratch[2 * NW + i];
+            p.momz += scratch[3 * NW + i];
+            p.umax2 = fmax(p.umax2, scratch[4 * NW + i]);
+            p.mumin = fmin(p.mumin, scratch[5 * NW + i]);
+            p.mumax = fmax(p.mumax, scratch[6 * NW + i]);
+            p.status |= uscratch[i];
+        }
+        *out = p;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned blowup_bits(T rho, T ux, T uy, T uz, double rho_max) {
+    unsigned s = 0;
+    if (!(dev_finite(rho) && dev_finite(ux) && dev_finite(uy) && dev_finite(uz))) s |= 1u;
+    if (!(rho > T(0))) s |= 2u;
+    if ((double)rho >= rho_max) s |= 4u;
+    return s;
+}
+
+}  // namespace lbm

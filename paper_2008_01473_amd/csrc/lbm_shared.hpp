@@ -1,0 +1,62 @@
+// Plain data records shared by the host runtime and the kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kMaxQ = 19;
+
+// Scheme variants compiled into the kernels.
+enum Variant : int {
+    kStdChempot = 0,   // Eq. 13 right: F = grad(rho/3) - rho grad(mu)
+    kStdPtensor = 1,   // Eq. 13 left:  F = grad(rho/3) - div P, P from Eqs. 4-5
+    kImproved = 2      // Eq. 24, Eq. 27, Eqs. 28-29
+};
+
+// Per-lattice record, uploaded once at bind time.
+struct LatticeRec {
+    int nx, ny, nz, eos;
+    int slow_x, slow_y, slow_z, q;      // slow_*: extent too small for single-step wrap
+    long long state_offset;             // first node of this lattice in the state buffers
+    long long field_offset;             // first node of this lattice in field arrays
+    long long nnodes;
+    double a, b, RT, kappa, omega, rho_max;
+    double rho_ref, pm_ref, mu_ref;     // FP32 deviation reference (zero for FP64)
+    double fbar[kMaxQ];                 // reference populations f_eq(rho_ref, 0, pm_ref)
+    int tile_begin, tile_end;           // range of this lattice's tiles in the tile list
+};
+
+// One unit of work: an output tile (2D) or an output column chunk (3D).
+struct Tile {
+    int lat, x0, y0, z0, zn, pad0, pad1, pad2;
+};
+
+// Per-tile partial diagnostics, reduced per lattice in a fixed order.
+struct DiagPartial {
+    double mass, momx, momy, momz, umax2, mumin, mumax;
+    unsigned int status, pad;
+};
+
+// Per-lattice reduced diagnostics (device side image of lbm_diag's sums).
+struct DiagOut {
+    double mass, momx, momy, momz, umax, mumin, mumax;
+    unsigned int status, pad;
+};
+
+struct StepArgs {
+    const void* src;          // state at time t (post-collision at t-1, unstreamed)
+    void* dst;                // state at time t+1
+    const LatticeRec* recs;
+    const Tile* tiles;
+    int ntiles;
+    int tiles_per_xcd;        // XCD-aware block -> tile mapping
+    DiagPartial* partial;     // one per tile
+    unsigned int* status;     // one per lattice (sticky blow-up flags)
+    double* rho_out;          // fields mode outputs (may be null)
+    double* u_out;
+    double* mu_out;
+    long long field_total;    // total nodes of all lattices (vector-field stride)
+};
+
+}  // namespace lbm

@@ -1,0 +1,317 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Float64 bar: relative error per field <= 1e-12 (populations, rho, u with a 1e-8
+floor, mu).  Inputs are the seeded synthetic fields of paper_2008_01473_amd.inputs,
+shared by both sides; the coexistence densities come from the oracle's Maxwell
+construction."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import eos as oeos
+from oracle import model
+from paper_2008_01473_amd import inputs
+from parity_util import compare, oracle_params, oracle_run, rel_err, shape_of
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2008_01473_amd import runtime  # noqa: E402  (raises if liblbm.so is missing)
+
+VARIANTS = [("improved", "chempot"), ("standard", "chempot"), ("standard", "ptensor")]
+
+
+def _maxwell(eos, t, a=None, b=None):
+    E = oeos.make_eos(eos, a, b)
+    return oeos.maxwell(E, t)
+
+
+def _droplet(shape, eos, t, r, a=None, noise=1e-4, seed=0):
+    m = _maxwell(eos, t, a)
+    return inputs.droplet(shape, m["rho_g"], m["rho_l"], r, 5.0, noise=noise, seed=seed)
+
+
+@pytest.mark.parametrize("scheme,form", VARIANTS)
+@pytest.mark.parametrize("eos", ["vdW", "CS"])
+def test_d2q9_fp64_ragged_droplet(scheme, form, eos):
+    p = runtime.params("D2Q9", 70, 45, 1, eos=eos, T_over_Tc=0.8, kappa=0.02, tau=0.8, scheme=scheme,
+                       force_form=form)
+    rho0 = _droplet((45, 70), eos, 0.8, 12.0)
+    print(f"case D2Q9 fp64 {scheme}/{form} {eos} 70x45", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [0, 1, 10, 100])
+    compare(sim, p, refs[0])
+    t = 0
+    for s in (1, 10, 100):
+        sim.step(s - t)
+        t = s
+        compare(sim, p, refs[s])
+    sim.close()
+
+
+@pytest.mark.parametrize("scheme", ["improved", "standard"])
+def test_flat_interface_256x4_config(scheme):
+    """vdW a = 9/49, b = 2/21, T/Tc = 0.9, kappa = 0.01, tau = 1.0, tanh slab of
+    width 4 between the Maxwell densities plus U(-1e-4, 1e-4) noise (seed 0)."""
+    p = runtime.params("D2Q9", 256, 4, 1, eos="vdW", a=9.0 / 49.0, T_over_Tc=0.9, kappa=0.01, tau=1.0,
+                       scheme=scheme)
+    m = _maxwell("vdW", 0.9, a=9.0 / 49.0)
+    rho0 = inputs.slab((4, 256), m["rho_g"], m["rho_l"], 4.0, noise=1e-4, seed=0)
+    print(f"case D2Q9 256x4 {scheme}", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    steps = [1, 10, 100, 1000]
+    refs = oracle_run(p, rho0, steps)
+    t = 0
+    for s in steps:
+        sim.step(s - t)
+        t = s
+        compare(sim, p, refs[s])
+    d = sim.diagnostics()[0]
+    assert d["mass"] == pytest.approx(float(rho0.sum()), rel=1e-13)
+    sim.close()
+
+
+@pytest.mark.parametrize("scheme,form", VARIANTS)
+def test_d3q19_fp64_droplet(scheme, form):
+    p = runtime.params("D3Q19", 20, 18, 16, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=0.9, scheme=scheme,
+                       force_form=form)
+    rho0 = _droplet((16, 18, 20), "vdW", 0.8, 5.0)
+    print(f"case D3Q19 fp64 {scheme}/{form} 20x18x16", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [1, 5, 20])
+    t = 0
+    for s in (1, 5, 20):
+        sim.step(s - t)
+        t = s
+        compare(sim, p, refs[s])
+    sim.close()
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_every_tile_shape_gives_identical_populations(lattice):
+    shape = (45, 70) if lattice == "D2Q9" else (16, 18, 20)
+    nx, ny = shape[-1], shape[-2]
+    nz = 1 if lattice == "D2Q9" else shape[0]
+    p = runtime.params(lattice, nx, ny, nz, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    rho0 = _droplet(shape, "vdW", 0.8, 6.0)
+    outs = []
+    sim = runtime.LBM(p)
+    for s in range(sim.num_tile_shapes()):
+        print(f"case {lattice} tile shape {s}", flush=True)
+        sim.set_tile_shape(s)
+        sim.init(rho0)
+        sim.step(7)
+        outs.append(sim.get_f().cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    sim.close()
+
+
+def test_graph_replay_equals_single_launches_and_is_deterministic():
+    p = runtime.params("D2Q9", 64, 64, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    rho0 = _droplet((64, 64), "vdW", 0.8, 14.0)
+    res = []
+    for graphs in (True, False, True):
+        sim = runtime.LBM(p)
+        sim.use_graphs(graphs)
+        sim.init(rho0)
+        sim.step(37)
+        res.append(sim.get_f().cpu())
+        sim.close()
+    assert torch.equal(res[0], res[1]) and torch.equal(res[0], res[2])
+
+
+def test_batch_of_unequal_lattices_matches_each_alone():
+    specs = [
+        dict(nx=40, ny=40, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=0.8, r=9.0),
+        dict(nx=64, ny=16, eos="vdW", T_over_Tc=0.9, kappa=0.01, tau=0.7, r=None),
+        dict(nx=33, ny=47, eos="CS", T_over_Tc=0.8, kappa=0.015, tau=1.1, r=8.0),
+    ]
+    ps, rhos = [], []
+    for s in specs:
+        ps.append(runtime.params("D2Q9", s["nx"], s["ny"], 1, eos=s["eos"], T_over_Tc=s["T_over_Tc"],
+                                 kappa=s["kappa"], tau=s["tau"]))
+        m = _maxwell(s["eos"], s["T_over_Tc"])
+        if s["r"]:
+            rhos.append(inputs.droplet((s["ny"], s["nx"]), m["rho_g"], m["rho_l"], s["r"], 5.0, noise=1e-4))
+        else:
+            rhos.append(inputs.slab((s["ny"], s["nx"]), m["rho_g"], m["rho_l"], 4.0, noise=1e-4))
+    sim = runtime.LBM(ps)
+    sim.init(np.concatenate([r.ravel() for r in rhos]))
+    sim.step(20)
+    for i, (p, r0) in enumerate(zip(ps, rhos)):
+        ref = oracle_run(p, r0, [20])[20]
+        compare(sim, p, ref, lat_index=i)
+    diags = sim.diagnostics()
+    for d, r0 in zip(diags, rhos):
+        assert d["mass"] == pytest.approx(float(r0.sum()), rel=1e-13)
+        assert d["status"] == 0
+    sim.close()
+
+
+def test_blowup_is_flagged_and_isolated():
+    """A lattice started outside the EOS domain (rho >= 1/b) is flagged and frozen;
+    the other lattice of the batch evolves exactly as when run alone."""
+    p_bad = runtime.params("D2Q9", 32, 32, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    p_ok = runtime.params("D2Q9", 48, 40, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    bad = np.full((32, 32), 2.0)
+    bad[10, 10] = 1.2 / (2.0 / 21.0)          # beyond the vdW packing limit 1/b
+    good = _droplet((40, 48), "vdW", 0.8, 9.0)
+    sim = runtime.LBM([p_bad, p_ok])
+    sim.init(np.concatenate([bad.ravel(), good.ravel()]))
+    sim.step(10)
+    d = sim.diagnostics()
+    assert d[0]["status"] != 0 and d[1]["status"] == 0
+    off = sim.offsets()[1]
+    f_batch = sim.get_f()[:, off:].cpu()
+    solo = runtime.LBM(p_ok)
+    solo.init(good)
+    solo.step(10)
+    assert torch.equal(f_batch, solo.get_f().cpu())
+    with pytest.raises(runtime._lib.LBMError):
+        sim.diagnostics(raise_on_blowup=True)
+    sim.close()
+    solo.close()
+
+
+def test_state_round_trips_and_zero_steps():
+    p = runtime.params("D2Q9", 30, 20, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    rho0 = _droplet((20, 30), "vdW", 0.8, 6.0)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(0)
+    assert sim.time == 0
+    f0 = sim.get_f()
+    sim.set_f(f0)
+    assert torch.equal(sim.get_f(), f0)
+    st, t = sim.get_state()
+    sim.step(5)
+    f5 = sim.get_f().clone()
+    sim.set_state(st, t)
+    assert sim.time == 0
+    sim.step(5)
+    assert torch.equal(sim.get_f(), f5)
+    sim.close()
+
+
+def test_tiny_lattices_wrap_correctly():
+    # extents smaller than the stencil halo exercise the general periodic wrap
+    for (nx, ny) in ((5, 3), (1, 7), (9, 1)):
+        p = runtime.params("D2Q9", nx, ny, 1, T_over_Tc=0.9, kappa=0.02, tau=0.8)
+        rng = np.random.default_rng(nx * 10 + ny)
+        rho0 = 2.0 + rng.uniform(-0.3, 0.3, size=(ny, nx))
+        sim = runtime.LBM(p)
+        sim.init(rho0)
+        sim.step(3)
+        compare(sim, p, oracle_run(p, rho0, [3])[3])
+        sim.close()
+    p = runtime.params("D3Q19", 3, 4, 2, T_over_Tc=0.9, kappa=0.02, tau=0.8)
+    rho0 = 2.0 + np.random.default_rng(1).uniform(-0.3, 0.3, size=(2, 4, 3))
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(3)
+    compare(sim, p, oracle_run(p, rho0, [3])[3])
+    sim.close()
+
+
+def test_initial_velocity_field():
+    p = runtime.params("D2Q9", 40, 32, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    rho0 = _droplet((32, 40), "vdW", 0.8, 8.0)
+    u0 = np.zeros((2, 32, 40))
+    u0[0] = 0.05
+    u0[1] = 0.02 * np.sin(2 * math.pi * np.arange(40) / 40)[None, :]
+    sim = runtime.LBM(p)
+    sim.init(rho0, u0)
+    sim.step(10)
+    compare(sim, p, oracle_run(p, rho0, [10], u0=u0)[10])
+    sim.close()
+
+
+@pytest.mark.parametrize("lattice,scheme", [("D2Q9", "improved"), ("D2Q9", "standard"), ("D3Q19", "improved")])
+def test_fp32_deviation_storage_tracks_fp64(lattice, scheme):
+    """FP32 deviation storage: fields within float32 round-off of the oracle after a
+    few steps (rho relative 2e-6, u absolute 2e-6, populations 2e-6 of max f)."""
+    shape = (45, 70) if lattice == "D2Q9" else (16, 18, 20)
+    nx, ny = shape[-1], shape[-2]
+    nz = 1 if lattice == "D2Q9" else shape[0]
+    p = runtime.params(lattice, nx, ny, nz, T_over_Tc=0.8, kappa=0.02, tau=0.8, scheme=scheme, precision="fp32")
+    rho0 = _droplet(shape, "vdW", 0.8, 6.0 if lattice == "D3Q19" else 12.0)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(10)
+    f_ref, fl = oracle_run(p, rho0, [10])[10]
+    errs = {}
+    off, n = 0, int(np.prod(shape))
+    f = sim.get_f()[:, off:off + n].reshape((-1,) + shape)
+    rho, u, mu = sim.moments()
+    errs["f"] = rel_err(f, f_ref)
+    errs["rho"] = rel_err(rho.reshape(shape), fl["rho"])
+    errs["u_abs"] = float((u.reshape((-1,) + shape).cpu() - fl["u"]).abs().max())
+    errs["mu_abs"] = float((mu.reshape(shape).cpu() - fl["mu"]).abs().max())
+    print("fp32 errors", errs, flush=True)
+    assert errs["f"] < 2e-6 and errs["rho"] < 2e-6 and errs["u_abs"] < 2e-6 and errs["mu_abs"] < 2e-6
+    sim.close()
+
+
+def test_full_size_512sq_cs_droplet_one_step():
+    """The 512 x 512 Carnahan-Starling droplet (r = 80, T/Tc = 0.8, kappa = 0.01,
+    tau = 0.8) in the launch configuration the benchmark times: whole-lattice
+    parity after one step and after two graph-replayed steps."""
+    p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8)
+    rho0 = _droplet((512, 512), "CS", 0.8, 80.0)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [1, 3])
+    sim.step(1)
+    compare(sim, p, refs[1])
+    sim.step(2)
+    compare(sim, p, refs[3])
+    sim.close()
+
+
+def _window_oracle(p, rho0, center, radius, steps):
+    """Oracle on a periodic window of the initial field around `center`; the central
+    node is exact for `steps` steps when radius >= 5 * steps + 1."""
+    shape = shape_of(p)
+    idx = [np.arange(c - radius, c + radius + 1) % n for c, n in zip(center, shape)]
+    sub = rho0[np.ix_(*idx)]
+    prm = oracle_params(p)
+    f = model.run(model.init(torch.as_tensor(sub), prm), prm, steps)
+    return f[(slice(None),) + (radius,) * len(shape)], model.fields(f, prm)
+
+
+def test_full_size_256cube_d3q19_sampled_nodes():
+    """The 256^3 D3Q19 vdW droplet (r = 40, T/Tc = 0.7, kappa = 0.02, tau = 1.0, FP32
+    deviation storage) in the benchmark's launch configuration: one step, sampled
+    nodes against oracle windows, and exact mass conservation in the FP64 sums."""
+    p = runtime.params("D3Q19", 256, 256, 256, eos="vdW", T_over_Tc=0.7, kappa=0.02, tau=1.0, precision="fp32")
+    rho0 = _droplet((256, 256, 256), "vdW", 0.7, 40.0)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(1)
+    f = sim.get_f()
+    rng = np.random.default_rng(7)
+    samples = [(128, 128, 88), (128, 168, 128), (0, 0, 0), (255, 17, 128)] + \
+        [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(4)]
+    fmax = 0.0
+    worst = 0.0
+    for c in samples:
+        fr, _ = _window_oracle(p, rho0, c, 7, 1)
+        node = (c[0] * 256 + c[1]) * 256 + c[2]
+        g = f[:, node].cpu()
+        worst = max(worst, float((g - fr).abs().max()))
+        fmax = max(fmax, float(fr.abs().max()))
+    assert worst / fmax < 2e-6, worst / fmax
+    sim.step(1)
+    rho, _, _ = sim.moments()
+    d = sim.diagnostics()[0]
+    assert d["mass"] == pytest.approx(float(rho0.sum()), rel=1e-6)
+    sim.close()
