@@ -1,6 +1,11 @@
 """Helpers of the GPU-vs-oracle parity tests: build matching oracle parameters,
 run the oracle, compare fields with the relative error of a field,
     err_X = max |X_gpu - X_oracle| / max(max |X_oracle|, floor_X).
+Floors: u = 1e-2, mu = 1e-3, none for populations and rho.  The velocity is a
+first moment of populations of size O(rho/9), so its rounding error follows the
+populations' (absolute, in lattice units) whatever |u| is; once the improved
+scheme has damped |u| a relative bar on u alone would tighten without limit.
+With the floor, |u| < 1e-2 is held to 1e-14 absolute (lattice units).
 """
 
 import numpy as np
@@ -46,7 +51,7 @@ def oracle_run(p, rho0, steps_list, u0=None):
     return out
 
 
-def compare(sim, p, ref, lat_index=0, f_tol=1e-12, fields_tol=1e-12, u_floor=1e-8):
+def compare(sim, p, ref, lat_index=0, f_tol=1e-12, fields_tol=1e-12, u_floor=1e-2):
     """Compare populations and fields of lattice `lat_index` of `sim` against an
     oracle (f, fields) pair.  Returns the dict of relative errors."""
     f_ref, fl = ref

@@ -39,9 +39,11 @@ def _droplet(shape, eos, t, r, a=None, noise=1e-4, seed=0):
 @pytest.mark.parametrize("scheme,form", VARIANTS)
 @pytest.mark.parametrize("eos", ["vdW", "CS"])
 def test_d2q9_fp64_ragged_droplet(scheme, form, eos):
-    p = runtime.params("D2Q9", 70, 45, 1, eos=eos, T_over_Tc=0.8, kappa=0.02, tau=0.8, scheme=scheme,
+    # the standard scheme with the CS EOS blows up at T/Tc = 0.8 (oracle and GPU alike)
+    T = 0.9 if (eos == "CS" and scheme == "standard") else 0.8
+    p = runtime.params("D2Q9", 70, 45, 1, eos=eos, T_over_Tc=T, kappa=0.02, tau=0.8, scheme=scheme,
                        force_form=form)
-    rho0 = _droplet((45, 70), eos, 0.8, 12.0)
+    rho0 = _droplet((45, 70), eos, T, 12.0)
     print(f"case D2Q9 fp64 {scheme}/{form} {eos} 70x45", flush=True)
     sim = runtime.LBM(p)
     sim.init(rho0)
