@@ -20,13 +20,13 @@
 
 namespace lbm {
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
-                            bool fields);
+                            int mode);
 hipError_t d2q9_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
                             long long total, hipStream_t s, int precision, int variant);
 hipError_t d2q9_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
                                hipStream_t s, int precision, bool get);
 hipError_t d3q19_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
-                             bool fields);
+                             int mode);
 hipError_t d3q19_launch_init(void* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
                              long long total, hipStream_t s, int precision, int variant);
 hipError_t d3q19_launch_convert(void* state, const LatticeRec* recs, int nlat, double* f, long long total,
@@ -233,7 +233,7 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     return R;
 }
 
-hipError_t launch_step(lbm_ctx* h, const StepArgs& a, bool fields, hipStream_t s) {
+hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
     const int ntiles = (int)h->tiles.size();
     const int per = (ntiles + 7) / 8;
     StepArgs b = a;
@@ -241,8 +241,8 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, bool fields, hipStream_t s
     b.tiles_per_xcd = per;
     const int grid = 8 * per;
     if (grid == 0) return hipSuccess;
-    if (h->lattice == LBM_D2Q9) return d2q9_launch_step(b, grid, s, h->precision, h->variant, h->shape, fields);
-    return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->shape, fields);
+    if (h->lattice == LBM_D2Q9) return d2q9_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
+    return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
 }
 
 StepArgs base_args(lbm_ctx* h) {
@@ -265,12 +265,12 @@ int upload_tables(lbm_ctx* h) {
     return LBM_OK;
 }
 
-int enqueue_steps(lbm_ctx* h, int n, hipStream_t s) {
+int enqueue_steps(lbm_ctx* h, int n, hipStream_t s, int mode = kStep) {
     for (int i = 0; i < n; ++i) {
         StepArgs a = base_args(h);
         a.src = h->buf[h->cur];
         a.dst = h->buf[h->cur ^ 1];
-        HIP_TRY(launch_step(h, a, false, s));
+        HIP_TRY(launch_step(h, a, mode, s));
         h->cur ^= 1;
     }
     return LBM_OK;
@@ -432,24 +432,24 @@ int lbm_step(lbm_ctx* h, int n) {
     if (!h->inited) return fail(LBM_ERR_STATE, "lbm_init or lbm_set_f first");
     if (n == 0) return LBM_OK;
     const long long t0 = h->t;
-    if (!h->use_graphs || n < 2) {
-        int rc = enqueue_steps(h, n, h->stream);
-        if (rc != LBM_OK) return rc;
-    } else {
-        int left = n;
-        while (left >= 2) {
-            const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
+    // all but the last step: graph replays of even length (the current buffer
+    // is unchanged by an even number of steps), then single launches
+    int body = n - 1;
+    if (h->use_graphs) {
+        while (body >= 2) {
+            const int len = body >= kGraphChunk ? kGraphChunk : (body & ~1);
             hipGraphExec_t ex;
             int rc = graph_for(h, len, &ex);
             if (rc != LBM_OK) return rc;
             HIP_TRY(hipGraphLaunch(ex, h->stream));
-            left -= len;     // len is even: the current buffer is unchanged
-        }
-        if (left) {
-            int rc = enqueue_steps(h, left, h->stream);
-            if (rc != LBM_OK) return rc;
+            body -= len;
         }
     }
+    int rc = enqueue_steps(h, body, h->stream, kStep);
+    if (rc != LBM_OK) return rc;
+    // the last step also reduces the diagnostics of its input time level
+    rc = enqueue_steps(h, 1, h->stream, kStepDiag);
+    if (rc != LBM_OK) return rc;
     h->t = t0 + n;
     h->t_diag = h->t - 1;
     return LBM_OK;
@@ -460,7 +460,7 @@ int lbm_prepare_steps(lbm_ctx* h, int n) {
     if (n < 0) return fail(LBM_ERR_ARG, "n must be >= 0");
     if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
     if (!h->use_graphs) return LBM_OK;
-    int left = n;
+    int left = n - 1;
     while (left >= 2) {
         const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
         hipGraphExec_t ex;
@@ -480,7 +480,7 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu) {
     a.rho_out = rho;
     a.u_out = u;
     a.mu_out = mu;
-    HIP_TRY(launch_step(h, a, true, h->stream));
+    HIP_TRY(launch_step(h, a, kFields, h->stream));
     h->t_diag = h->t;
     return LBM_OK;
 }

@@ -145,8 +145,9 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 //   B  mu = mu_EOS(rho) - kappa lap(rho) on tile + 2 (Eq. 2); P on tile + 2 (P-tensor form)
 //   C  F (Eq. 13 / Eq. 24), u = (j + F/2)/rho (Eq. 12), psi = phi u (Eq. 29) on tile + 1
 //   D  collision (Eq. 9 / Eq. 28 with Lambda = I/tau) and store, or field output
-// FIELDS = true writes rho, u, mu of the current time level instead of colliding.
-template <typename S, typename T, int V, int BX, int BY, bool FIELDS>
+// MODE (lbm::Mode) selects collide-and-store, the same plus per-tile
+// diagnostics, or writing rho, u, mu of the current time level.
+template <typename S, typename T, int V, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
@@ -183,19 +184,24 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
 
-    // ---- stage A: interior node owned by this thread (kept in registers) ----
+    // ---- stage A: the interior node owned by this thread (kept in registers for
+    // stage D) and up to HP nodes of the three halo rings; every load is issued
+    // before any is used.
+    constexpr int HALO = H3 * W3 - NT;
+    constexpr int HP = (HALO + NT - 1) / NT;
     T fown[9];
+    T fh[HP][9];
+    int hpos[HP];
     {
         const int gx = x0 + lx0, gy = y0 + ly0;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
         pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, fown);
-        s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
-        s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
-        s_b[(ly0 + 1) * W1 + lx0 + 1] = jy9(fown);
     }
-    // ---- stage A: the three halo rings ----
-    for (int k = tid; k < H3 * W3 - NT; k += NT) {
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+        int k = tid + q * NT;
+        k = k < HALO ? k : HALO - 1;          // idle lanes repeat the last halo node
         int lx, ly;
         if (k < 3 * W3) {
             ly = k / W3; lx = k % W3;
@@ -208,15 +214,25 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             const int c = k3 % 6;
             lx = c < 3 ? c : W3 - 6 + c;
         }
+        hpos[q] = ly * W3 + lx;
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        T f[9];
-        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, f);
-        s_rho[ly * W3 + lx] = rho_ref + sum9(f);
-        if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
-            s_a[(ly - 2) * W1 + lx - 2] = jx9(f);
-            s_b[(ly - 2) * W1 + lx - 2] = jy9(f);
+        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, fh[q]);
+    }
+    s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
+    s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
+    s_b[(ly0 + 1) * W1 + lx0 + 1] = jy9(fown);
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+        if (tid + q * NT < HALO) {
+            const int pos = hpos[q];
+            const int ly = pos / W3, lx = pos - ly * W3;
+            s_rho[pos] = rho_ref + sum9(fh[q]);
+            if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
+                s_a[(ly - 2) * W1 + lx - 2] = jx9(fh[q]);
+                s_b[(ly - 2) * W1 + lx - 2] = jy9(fh[q]);
+            }
         }
     }
     __syncthreads();
@@ -285,7 +301,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const T Fx = s_F[tid], Fy = s_F[NT + tid], ux = s_u[tid], uy = s_u[NT + tid];
         const T drho = sum9(fown);
         const int node = gy * nx + gx;
-        if constexpr (FIELDS) {
+        if constexpr (MODE == kFields) {
             const long long o = R.field_offset + node;
             if (args.rho_out) args.rho_out[o] = (double)r;
             if (args.mu_out) args.mu_out[o] = (double)mu;
@@ -318,8 +334,15 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         acc.mumax = (double)mu;
         acc.status = blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
     }
-    block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
-    if (threadIdx.x == 0 && args.partial[t_idx].status != 0u) atomicOr(args.status + tile.lat, args.partial[t_idx].status);
+    if constexpr (MODE == kStep) {
+        if (acc.status) atomicOr(args.status + tile.lat, acc.status);
+    } else {
+        block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+        if (threadIdx.x == 0) {
+            const unsigned st = args.partial[t_idx].status;
+            if (st) atomicOr(args.status + tile.lat, st);
+        }
+    }
 }
 
 // Initialisation: f(x, 0) = f_eq(rho0, u0) (minus fbar), written where a pull
@@ -402,20 +425,22 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 
 namespace {
 template <typename S, typename T, int V, int BX, int BY>
-hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, bool fields) {
-    if (fields)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, s, a);
+hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
+    if (mode == kFields)
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields>), dim3(grid), dim3(BX * BY), 0, s, a);
+    else if (mode == kStepDiag)
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag>), dim3(grid), dim3(BX * BY), 0, s, a);
     else
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep>), dim3(grid), dim3(BX * BY), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename S, typename T, int V>
-hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, bool fields, int shape) {
+hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, int fields, int shape) {
     switch (shape) {
-        case 0: return launch_step_t<S, T, V, 32, 8>(a, grid, s, fields);
-        case 1: return launch_step_t<S, T, V, 64, 4>(a, grid, s, fields);
-        case 2: return launch_step_t<S, T, V, 32, 16>(a, grid, s, fields);
+        case 0: return launch_step_t<S, T, V, 32, 16>(a, grid, s, fields);
+        case 1: return launch_step_t<S, T, V, 64, 8>(a, grid, s, fields);
+        case 2: return launch_step_t<S, T, V, 32, 8>(a, grid, s, fields);
         case 3: return launch_step_t<S, T, V, 16, 16>(a, grid, s, fields);
         default: return hipErrorInvalidValue;
     }
@@ -423,12 +448,12 @@ hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, bool fields,
 }  // namespace
 
 extern const int kD2Q9Shapes[][2];
-const int kD2Q9Shapes[][2] = {{32, 8}, {64, 4}, {32, 16}, {16, 16}};
+const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}};
 extern const int kNumD2Q9Shapes;
 const int kNumD2Q9Shapes = 4;
 
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
-                            bool fields) {
+                            int fields) {
     if (precision == 0) {
         switch (variant) {
             case kStdChempot: return launch_shape<double, double, kStdChempot>(a, grid, s, fields, shape);

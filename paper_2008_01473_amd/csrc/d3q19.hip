@@ -171,7 +171,7 @@ __device__ __forceinline__ void equilibrium(T feq[19], T rho, T drho, T ux, T uy
 //   D  collide and store slice za - 3 (the thread's own populations, pulled
 //      three iterations earlier, wait in a register FIFO when FIFO is set)
 // Rings hold 4 slices (slot = (z - z0 + 8) & 3); F and u of the tile hold 2.
-template <typename S, typename T, int V, int BX, int BY, bool FIELDS>
+template <typename S, typename T, int V, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
     constexpr int W3 = BX + 6, H3 = BY + 6, A3 = W3 * H3;
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             }
             const T drho = sum19(f);
             const int node = zd * NXY + gy0 * nx + gx0;
-            if constexpr (FIELDS) {
+            if constexpr (MODE == kFields) {
                 const long long o = R.field_offset + node;
                 if (args.rho_out) args.rho_out[o] = (double)r;
                 if (args.mu_out) args.mu_out[o] = (double)mu;
@@ -444,10 +444,14 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         }
         __syncthreads();
     }
-    block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
-    if (threadIdx.x == 0) {
-        const unsigned st = args.partial[t_idx].status;
-        if (st != 0u) atomicOr(args.status + tile.lat, st);
+    if constexpr (MODE == kStep) {
+        if (acc.status) atomicOr(args.status + tile.lat, acc.status);
+    } else {
+        block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+        if (threadIdx.x == 0) {
+            const unsigned st = args.partial[t_idx].status;
+            if (st != 0u) atomicOr(args.status + tile.lat, st);
+        }
     }
 }
 
@@ -529,15 +533,17 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 
 namespace {
 template <typename S, typename T, int V, int BX, int BY>
-hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, bool fields) {
-    if (fields)
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, s, a);
+hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
+    if (mode == kFields)
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kFields>), dim3(grid), dim3(BX * BY), 0, s, a);
+    else if (mode == kStepDiag)
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag>), dim3(grid), dim3(BX * BY), 0, s, a);
     else
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep>), dim3(grid), dim3(BX * BY), 0, s, a);
     return hipGetLastError();
 }
 template <typename S, typename T, int V>
-hipError_t launch3_shape(const StepArgs& a, int grid, hipStream_t s, bool fields, int shape) {
+hipError_t launch3_shape(const StepArgs& a, int grid, hipStream_t s, int fields, int shape) {
     switch (shape) {
         case 0: return launch3_t<S, T, V, 32, 8>(a, grid, s, fields);
         case 1: return launch3_t<S, T, V, 16, 16>(a, grid, s, fields);
@@ -553,7 +559,7 @@ extern const int kNumD3Q19Shapes;
 const int kNumD3Q19Shapes = 3;
 
 hipError_t d3q19_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
-                             bool fields) {
+                             int fields) {
     if (precision == 0) {
         switch (variant) {
             case kStdChempot: return launch3_shape<double, double, kStdChempot>(a, grid, s, fields, shape);

@@ -14,6 +14,13 @@ enum Variant : int {
     kImproved = 2      // Eq. 24, Eq. 27, Eqs. 28-29
 };
 
+// What a step-kernel launch does at its output nodes.
+enum Mode : int {
+    kStep = 0,         // collide and store; only the blow-up flags are checked
+    kStepDiag = 1,     // collide and store, and write the per-tile diagnostics
+    kFields = 2        // write rho, u, mu (and the diagnostics) of the current time level
+};
+
 // Per-lattice record, uploaded once at bind time.
 struct LatticeRec {
     int nx, ny, nz, eos;

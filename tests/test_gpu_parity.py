@@ -317,3 +317,19 @@ def test_full_size_256cube_d3q19_sampled_nodes():
     d = sim.diagnostics()[0]
     assert d["mass"] == pytest.approx(float(rho0.sum()), rel=1e-6)
     sim.close()
+
+
+def test_standard_scheme_droplet_instability_is_flagged():
+    """Sec. IV B: the standard scheme is unstable for the droplet at T/Tc = 0.7 (its
+    blow-up is detected and flagged), while the improved scheme at T/Tc = 0.75 stays
+    healthy (vdW a = 9/392, kappa = 0.02, tau = 1.0, 96 x 96, r = 20)."""
+    res = {}
+    for scheme, T in (("standard", 0.7), ("improved", 0.75)):
+        p = runtime.params("D2Q9", 96, 96, 1, eos="vdW", T_over_Tc=T, kappa=0.02, tau=1.0, scheme=scheme)
+        sim = runtime.LBM(p)
+        sim.init(_droplet((96, 96), "vdW", T, 20.0, noise=0.0))
+        sim.step(400)
+        res[scheme] = sim.diagnostics()[0]
+        sim.close()
+    assert res["standard"]["status"] != 0
+    assert res["improved"]["status"] == 0 and res["improved"]["max_u"] < 1e-2
