@@ -181,6 +181,40 @@ int lbm_set_state(lbm_ctx* h, const void* src_dev, long long step);
 /* Time level of the handle. */
 long long lbm_time(const lbm_ctx* h);
 
+/* Change kappa and T/T_c of lattice i (e.g. for finite-difference checks);
+ * synchronises the stream and re-uploads the parameter table. */
+int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc);
+
+/*
+ * Adjoint (vector-Jacobian products) of the D2Q9 step, for one lattice per
+ * handle with the improved scheme or the standard chemical-potential scheme.
+ * The step is Eqs. 7-14 (standard) or Eqs. 24-29 (improved) with
+ * Lambda = I/tau; its transpose runs the streaming backwards, applies the
+ * transposed stencils (the Eq. 17 gradient is antisymmetric and the Laplacian
+ * symmetric on a periodic lattice) and the local derivatives of the
+ * equilibrium, forcing and correction terms.  Arithmetic is float64.
+ *   state_t   raw state of time level t in this handle's storage format, as
+ *             returned by lbm_get_state (device, lbm_state_bytes)
+ *   lam_next  dL/df(t+1), device float64, layout of lbm_get_f ([9][N])
+ *   lam_out   dL/df(t), same layout (must not alias lam_next)
+ *   ws        device workspace of lbm_adjoint_workspace_bytes, caller-owned
+ *   grad      device float64[2], incremented by dL/dkappa and dL/d(T/Tc)
+ *             contributed by this step (fixed-order, deterministic sums)
+ * lbm_adjoint_fields: dL/df(t) for given cotangents of the fields of Eq. 12,
+ *   rho_bar [N] and u_bar [2][N] (either may be NULL = zero), plus the
+ *   parameter terms through mu.
+ * lbm_adjoint_init: dL/drho0 of the initialisation f = f_eq(rho0, u0 = 0) from
+ *   lam0 = dL/df(0); grad_rho0 [N] is overwritten, grad incremented.
+ * Returns LBM_ERR_UNSUPPORTED for D3Q19, batches or the pressure-tensor force.
+ */
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h);
+int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out, void* ws,
+                     double* grad);
+int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar,
+                       double* lam_out, void* ws, double* grad);
+int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double* grad_rho0, void* ws,
+                     double* grad);
+
 /* Maxwell construction (equal mu_EOS and p_EOS) of the chosen EOS at T/T_c, on
  * the host in float64.  Returns LBM_ERR_DOMAIN when there is no coexistence. */
 int lbm_maxwell(int eos, double a, double b, double R, double T_over_Tc,

@@ -55,6 +55,11 @@ SIGNATURES = {
     "lbm_maxwell": (c_int, [c_int, c_double, c_double, c_double, c_double, P(c_double), P(c_double),
                             P(c_double), P(c_double)]),
     "lbm_critical_temperature": (c_double, [c_int, c_double, c_double, c_double]),
+    "lbm_set_physics": (c_int, [c_void_p, c_int, c_double, c_double]),
+    "lbm_adjoint_workspace_bytes": (c_size_t, [c_void_p]),
+    "lbm_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lbm_adjoint_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lbm_adjoint_init": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_set_tile_shape": (c_int, [c_void_p, c_int]),
     "lbm_get_tile_shape": (c_int, [c_void_p]),
     "lbm_num_tile_shapes": (c_int, [c_void_p]),

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["d2q9.hip", "d3q19.hip", "common.hip", "api.cpp", "maxwell.cpp"]
+SOURCES = ["d2q9.hip", "d3q19.hip", "adjoint.hip", "common.hip", "api.cpp", "maxwell.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -35,6 +35,10 @@ hipError_t launch_finalize(const DiagPartial* partial, const LatticeRec* recs, c
                            DiagOut* out, int nlat, hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+size_t adjoint_workspace_doubles(long long N);
+hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int precision, int improved, const void* state,
+                          const double* lam_in, double* lam_out, const double* rho_bar, const double* u_bar,
+                          const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s);
 extern const int kD2Q9Shapes[][2];
 extern const int kNumD2Q9Shapes;
 extern const int kD3Q19Shapes[][2];
@@ -643,6 +647,76 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
     h->t_diag = -1;
     return best;
+}
+
+int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
+    if (!h || i < 0 || i >= (int)h->recs.size()) return fail(LBM_ERR_ARG, "bad handle or lattice index");
+    if (!(kappa >= 0) || !(T_over_Tc > 0)) return fail(LBM_ERR_ARG, "kappa >= 0 and T_over_Tc > 0 required");
+    lbm_params& p = h->params[i];
+    p.kappa = kappa;
+    p.T_over_Tc = T_over_Tc;
+    LatticeRec& R = h->recs[i];
+    R.kappa = kappa;
+    R.RT = p.R * T_over_Tc * host::critical_temperature(p.eos, p.a, p.b, p.R);
+    if (h->bound) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return upload_tables(h);
+    }
+    return LBM_OK;
+}
+
+namespace {
+int adjoint_check(lbm_ctx* h) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->variant == kStdPtensor)
+        return fail(LBM_ERR_UNSUPPORTED,
+                    "the adjoint is implemented for one D2Q9 lattice, improved or chemical-potential standard scheme");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    return LBM_OK;
+}
+double adjoint_dRT(const lbm_ctx* h) {
+    const lbm_params& p = h->params[0];
+    return p.R * host::critical_temperature(p.eos, p.a, p.b, p.R);
+}
+}  // namespace
+
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h) {
+    if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1) return 0;
+    return align256(adjoint_workspace_doubles(h->recs[0].nnodes) * sizeof(double));
+}
+
+int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out, void* ws,
+                     double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!state_t || !lam_next || !lam_out || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
+    if (lam_next == lam_out) return fail(LBM_ERR_ARG, "lam_next and lam_out must not alias");
+    HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, state_t, lam_next,
+                           lam_out, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<double*>(ws), grad,
+                           h->stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar, double* lam_out,
+                       void* ws, double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!state_t || !lam_out || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
+    HIP_TRY(adjoint_launch(1, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, state_t, nullptr,
+                           lam_out, rho_bar, u_bar, nullptr, nullptr, reinterpret_cast<double*>(ws), grad,
+                           h->stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double* grad_rho0, void* ws,
+                     double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!rho0 || !lam0 || !grad_rho0 || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
+    HIP_TRY(adjoint_launch(2, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, nullptr, lam0,
+                           nullptr, nullptr, nullptr, rho0, grad_rho0, reinterpret_cast<double*>(ws), grad,
+                           h->stream));
+    return LBM_OK;
 }
 
 int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream) {
