@@ -133,6 +133,44 @@ def batch_spec(runtime, inputs, count=96, seed=0):
                         "T/Tc in [0.5,0.95], kappa in [0.005,0.02], tau=1.0, improved, fp32, one launch per step"}
 
 
+def adjoint_measure(torch, runtime, inputs, n_steps=4000):
+    """256 x 256 vdW droplet (r = 40, T/Tc = 0.75, kappa = 0.02, tau = 1.0), FP32
+    forward with sqrt(N) checkpoints, loss sum (rho_N - rho*)^2 + sum |u_N|^2:
+    times the forward and the backward (recompute + adjoint) passes."""
+    from paper_2008_01473_amd.adjoint import Rollout, rollout
+
+    m = runtime.maxwell("vdW", 0.75)
+    rho0 = inputs.droplet((256, 256), m["rho_g"], m["rho_l"], 40.0, 5.0, noise=1e-4, seed=0)
+    rng = np.random.default_rng(11)
+    target = inputs.droplet((256, 256), m["rho_g"], m["rho_l"], 40.0, 5.0) + \
+        0.01 * (m["rho_l"] - m["rho_g"]) * rng.uniform(-1, 1, size=(256, 256))
+    p = runtime.params("D2Q9", 256, 256, 1, eos="vdW", T_over_Tc=0.75, kappa=0.02, tau=1.0, scheme="improved",
+                       precision="fp32")
+    roll = Rollout(p)
+    tgt = torch.as_tensor(target).reshape(-1).cuda()
+    r0 = torch.as_tensor(rho0).reshape(-1).cuda().requires_grad_(True)
+    kd = torch.tensor(0.02, dtype=torch.float64, device="cuda", requires_grad=True)
+    td = torch.tensor(0.75, dtype=torch.float64, device="cuda", requires_grad=True)
+    roll.forward(r0.detach(), 0.02, 0.75, 64)          # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho_n, u_n = rollout(r0, kd, td, roll, n_steps)
+    loss = ((rho_n - tgt) ** 2).sum() + (u_n ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    roll.close()
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"name": "adjoint_d2q9_256_fp32", "steps": n_steps,
+            "workload": "D2Q9 256x256 vdW droplet r=40, T/Tc=0.75, kappa=0.02, tau=1.0, improved, fp32 forward, "
+                        f"{n_steps} steps, sqrt(N) checkpoints, float64 adjoint",
+            "forward_s": fwd, "backward_s": bwd, "fwd_plus_bwd_over_fwd": (fwd + bwd) / fwd,
+            "mlups": 65536 * n_steps / (fwd + bwd) / 1e6,
+            "grad_kappa": float(kd.grad), "grad_T_over_Tc": float(td.grad)}
+
+
 def cpu_baseline(torch, inputs, seconds):
     """The oracle (float64, CPU) on the primary lattice, as many whole steps as fit
     in about `seconds` (at least 2)."""
@@ -195,6 +233,12 @@ def main():
             ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),
             ("batch", lambda: batch_spec(runtime, inputs), max(20, args.steps // 20)),
         ]
+        if not only or "adjoint" in only:
+            r = adjoint_measure(torch, runtime, inputs)
+            r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
+            secondary.append(r)
+            print(f"[bench] adjoint: fwd {r['forward_s'] * 1e3:.1f} ms, bwd {r['backward_s'] * 1e3:.1f} ms, "
+                  f"(fwd+bwd)/fwd = {r['fwd_plus_bwd_over_fwd']:.1f}", file=sys.stderr, flush=True)
         for name, mk, k in jobs:
             if only and name not in only:
                 continue
