@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--only", default="", help="comma list of secondary names to run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graphs", action="store_true", help="one kernel launch per step (for counter runs)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape (no autotuning)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run the plain copy kernel on this many MiB, 5 times (traffic-counter calibration)")
     return ap.parse_args()
@@ -62,12 +63,15 @@ def timed_steps(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True):
+def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True, tune=0):
     """Build one workload, time it, return a result record."""
     p_list, rho0 = spec["params"], spec["rho0"]
     sim = runtime.LBM(p_list)
     sim.use_graphs(graphs)
     sim.init(rho0)
+    if tune:
+        sim.autotune(tune)          # times every tile shape on this state, keeps the fastest
+    shape = sim.tile_shape()
     ms = timed_steps(torch, sim, steps, warmup)
     Q = sim.Q
     word = 8 if p_list[0].precision == 0 else 4
@@ -88,6 +92,7 @@ def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True):
         "bytes_per_lup": 2 * Q * word,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS},
+        "tile": list(shape),
         "blown_up_lattices": blown,
         "max_u": max(d["max_u"] for d in diag),
     }
@@ -220,7 +225,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
         return
     graphs = not args.no_graphs
-    prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs)
+    tune = 0 if args.no_tune else 20
+    prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs, tune)
     print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step",
           file=sys.stderr, flush=True)
     secondary = []
@@ -242,7 +248,7 @@ def main():
         for name, mk, k in jobs:
             if only and name not in only:
                 continue
-            r = measure(torch, runtime, inputs, mk(), k, min(args.warmup, k), graphs)
+            r = measure(torch, runtime, inputs, mk(), k, min(args.warmup, k), graphs, tune)
             r["steps"] = k
             r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
             secondary.append(r)
@@ -265,7 +271,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": prim["workload"], "lattice": "D2Q9", "nodes": prim["nodes"],
-                   "bytes_per_lup": prim["bytes_per_lup"]},
+                   "bytes_per_lup": prim["bytes_per_lup"], "tile": prim["tile"]},
         "roofline": dict(prim["roofline"], traffic=None),
         "cpu_baseline": cpu,
         "secondary": secondary,

@@ -589,6 +589,12 @@ int lbm_describe_tile_shape(const lbm_ctx* h, int s, int* bx, int* by, int* bz) 
 
 int lbm_set_tile_shape(lbm_ctx* h, int s) {
     if (!h || s < 0 || s >= h->num_shapes()) return fail(LBM_ERR_ARG, "bad shape index");
+    {
+        int bx, by;
+        h->shape_dims(s, bx, by);
+        if (h->lattice == LBM_D3Q19 && h->precision == LBM_FP64 && bx * by > 256)
+            return fail(LBM_ERR_UNSUPPORTED, "this D3Q19 tile shape needs more LDS than float64 allows");
+    }
     std::vector<LatticeRec> rr = h->recs;
     std::vector<Tile> tt = h->plan(s, rr);
     if ((int)tt.size() > h->max_tiles) return fail(LBM_ERR_UNSUPPORTED, "tile list does not fit the workspace");

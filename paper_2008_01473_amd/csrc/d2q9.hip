@@ -20,18 +20,21 @@ namespace lbm {
 namespace d2q9 {
 
 // Pull the nine populations arriving at (xc, yc): f_a(x) = f*_a(x - e_a).
+// p[a] is the (wave-uniform) base of population a, so each load is a scalar
+// base plus a 32-bit lane offset.
 template <typename S, typename T>
-__device__ __forceinline__ void pull(const S* __restrict__ src, int N, int nx, int xm, int xc, int xp, int ym,
-                                     int yc, int yp, T f[9]) {
-    f[0] = (T)src[0 * N + yc * nx + xc];
-    f[1] = (T)src[1 * N + yc * nx + xm];
-    f[2] = (T)src[2 * N + ym * nx + xc];
-    f[3] = (T)src[3 * N + yc * nx + xp];
-    f[4] = (T)src[4 * N + yp * nx + xc];
-    f[5] = (T)src[5 * N + ym * nx + xm];
-    f[6] = (T)src[6 * N + ym * nx + xp];
-    f[7] = (T)src[7 * N + yp * nx + xp];
-    f[8] = (T)src[8 * N + yp * nx + xm];
+__device__ __forceinline__ void pull(const S* const (&p)[9], int nx, int xm, int xc, int xp, int ym, int yc,
+                                     int yp, T f[9]) {
+    const unsigned rc = (unsigned)(yc * nx), rm = (unsigned)(ym * nx), rp = (unsigned)(yp * nx);
+    f[0] = (T)ld_off(p[0], rc + xc);
+    f[1] = (T)ld_off(p[1], rc + xm);
+    f[2] = (T)ld_off(p[2], rm + xc);
+    f[3] = (T)ld_off(p[3], rc + xp);
+    f[4] = (T)ld_off(p[4], rp + xc);
+    f[5] = (T)ld_off(p[5], rm + xm);
+    f[6] = (T)ld_off(p[6], rm + xp);
+    f[7] = (T)ld_off(p[7], rp + xp);
+    f[8] = (T)ld_off(p[8], rp + xm);
 }
 
 template <typename T>
@@ -78,45 +81,27 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
                                         T Cyy, T omega) {
     const T usq = ux * ux + uy * uy;
     const T uF = ux * Fx + uy * Fy;
-    const T om2 = T(1) - T(0.5) * omega;
+    const T om1 = T(1) - omega, om2 = T(1) - T(0.5) * omega;
     const T r9 = rho * T(1.0 / 9.0), r36 = rho * T(1.0 / 36.0);
     const T Ca = (Cxx - T(2) * Cyy) * T(1.0 / 6.0);   // +-x
     const T Cb = (Cyy - T(2) * Cxx) * T(1.0 / 6.0);   // +-y
     const T Cd = (Cxx + Cyy) * T(1.0 / 6.0);          // diagonals
-    const T Cr = -T(2) * Cd;                          // rest
     {
         const T feq = drho - T(5.0 / 3.0) * dpm - T(2.0 / 3.0) * rho * usq;
         const T G = T(4.0 / 9.0) * (T(-3) * uF);
-        f[0] = f[0] - omega * (f[0] - feq) + om2 * (G + Cr);
+        f[0] = om1 * f[0] + omega * feq + om2 * (G - T(2) * Cd);
     }
-    const T ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
-    const T ud = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
-#define LBM_AXIS(a, EX, EY, CC)                                                             \
-    {                                                                                       \
-        const T eu = T(EX) * ux + T(EY) * uy;                                               \
-        const T eF = T(EX) * Fx + T(EY) * Fy;                                               \
-        const T feq = ua + r9 * (T(3) * eu + T(4.5) * eu * eu) - T(0.5) * php * eu;         \
-        const T G = T(1.0 / 9.0) * (T(3) * (eF - uF) + T(9) * eu * eF);                     \
-        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + CC);                                \
-    }
-#define LBM_DIAG(a, EX, EY)                                                                 \
-    {                                                                                       \
-        const T eu = T(EX) * ux + T(EY) * uy;                                               \
-        const T eF = T(EX) * Fx + T(EY) * Fy;                                               \
-        const T feq = ud + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;       \
-        const T G = T(1.0 / 36.0) * (T(3) * (eF - uF) + T(9) * eu * eF);                    \
-        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + Cd);                                \
-    }
-    LBM_AXIS(1, 1, 0, Ca)
-    LBM_AXIS(2, 0, 1, Cb)
-    LBM_AXIS(3, -1, 0, Ca)
-    LBM_AXIS(4, 0, -1, Cb)
-    LBM_DIAG(5, 1, 1)
-    LBM_DIAG(6, -1, 1)
-    LBM_DIAG(7, -1, -1)
-    LBM_DIAG(8, 1, -1)
-#undef LBM_AXIS
-#undef LBM_DIAG
+    // axis pairs: w = 1/9, php coefficient -1/2;  diagonal pairs: w = 1/36, +1/4
+    const T Ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
+    const T Ud = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+    const T oa = T(3) * r9 - T(0.5) * php, od = T(3) * r36 + T(0.25) * php;
+    const T ga = T(-3.0 / 9.0) * uF, gd = T(-3.0 / 36.0) * uF;
+    pair_update<T>(f[1], f[3], ux, Fx, Ua, T(4.5) * r9, oa, T(1.0), T(1.0 / 3.0), ga, Ca, omega, om1, om2);
+    pair_update<T>(f[2], f[4], uy, Fy, Ua, T(4.5) * r9, oa, T(1.0), T(1.0 / 3.0), ga, Cb, omega, om1, om2);
+    pair_update<T>(f[5], f[7], ux + uy, Fx + Fy, Ud, T(4.5) * r36, od, T(0.25), T(1.0 / 12.0), gd, Cd, omega, om1,
+                   om2);
+    pair_update<T>(f[6], f[8], uy - ux, Fy - Fx, Ud, T(4.5) * r36, od, T(0.25), T(1.0 / 12.0), gd, Cd, omega, om1,
+                   om2);
 }
 
 // Equilibrium minus reference for initialisation (same closed forms, no force).
@@ -177,6 +162,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const int sx = R.slow_x, sy = R.slow_y;
     const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + R.state_offset * 9;
     S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + R.state_offset * 9;
+    const S* pp[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
     const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref;
@@ -196,7 +184,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int gx = x0 + lx0, gy = y0 + ly0;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, fown);
+        pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown);
     }
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
@@ -218,7 +206,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        pull<S, T>(src, N, nx, xm, xc, xp, ym, yc, yp, fh[q]);
+        pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
     }
     s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
     s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
@@ -323,7 +311,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             }
             collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) dst[a * N + node] = (S)fown[a];
+            for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fown[a]);
         }
         (void)pm_ref;
         acc.mass = (double)drho;

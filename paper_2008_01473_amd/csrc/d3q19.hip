@@ -32,10 +32,11 @@ __device__ constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 
 // offsets -1, 0, +1) are the wrapped x index, y*nx and z*nx*ny of the node's
 // neighbourhood.  Source of population a is x - e_a.
 template <typename S, typename T>
-__device__ __forceinline__ void pull(const S* __restrict__ src, int N, const int X[3], const int Y[3],
-                                     const int Z[3], T f[19]) {
+__device__ __forceinline__ void pull(const S* const (&p)[19], const int X[3], const int Y[3], const int Z[3],
+                                     T f[19]) {
 #pragma unroll
-    for (int a = 0; a < 19; ++a) f[a] = (T)src[a * N + Z[1 - EZ[a]] + Y[1 - EY[a]] + X[1 - EX[a]]];
+    for (int a = 0; a < 19; ++a)
+        f[a] = (T)ld_off(p[a], (unsigned)(Z[1 - EZ[a]] + Y[1 - EY[a]] + X[1 - EX[a]]));
 }
 
 template <typename T>
@@ -114,38 +115,35 @@ __device__ __forceinline__ void collide(T f[19], T rho, T drho, T ux, T uy, T uz
                                         T php, T Cxx, T Cyy, T Czz, T omega) {
     const T usq = ux * ux + uy * uy + uz * uz;
     const T uF = ux * Fx + uy * Fy + uz * Fz;
-    const T om2 = T(1) - T(0.5) * omega;
+    const T om1 = T(1) - omega, om2 = T(1) - T(0.5) * omega;
     const T r18 = rho * T(1.0 / 18.0), r36 = rho * T(1.0 / 36.0);
     const T S = Cxx + Cyy + Czz;
     const T k42 = T(1.0 / 42.0);
-    const T Cax[3] = {(T(7) * Cxx - T(6) * S) * k42, (T(7) * Cyy - T(6) * S) * k42, (T(7) * Czz - T(6) * S) * k42};
+    const T Cx = (T(7) * Cxx - T(6) * S) * k42, Cy = (T(7) * Cyy - T(6) * S) * k42, Cz = (T(7) * Czz - T(6) * S) * k42;
     const T Cxy = (T(7) * (Cxx + Cyy) - T(2) * S) * k42;
     const T Cxz = (T(7) * (Cxx + Czz) - T(2) * S) * k42;
     const T Cyz = (T(7) * (Cyy + Czz) - T(2) * S) * k42;
     {
         const T feq = drho - T(2) * dpm - T(0.5) * rho * usq;
         const T G = T(1.0 / 3.0) * (T(-3) * uF);
-        f[0] = f[0] - omega * (f[0] - feq) + om2 * (G + T(-5.0 / 21.0) * S);
+        f[0] = om1 * f[0] + omega * feq + om2 * (G + T(-5.0 / 21.0) * S);
     }
-    const T ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
-    const T ue = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
-#pragma unroll
-    for (int a = 1; a < 19; ++a) {
-        const T ex = T(EX[a]), ey = T(EY[a]), ez = T(EZ[a]);
-        const T eu = ex * ux + ey * uy + ez * uz;
-        const T eF = ex * Fx + ey * Fy + ez * Fz;
-        T feq, G, C;
-        if (a < 7) {
-            feq = ua + r18 * (T(3) * eu + T(4.5) * eu * eu) - php * eu;
-            G = T(1.0 / 18.0) * (T(3) * (eF - uF) + T(9) * eu * eF);
-            C = Cax[(a - 1) >> 1];
-        } else {
-            feq = ue + r36 * (T(3) * eu + T(4.5) * eu * eu) + T(0.25) * php * eu;
-            G = T(1.0 / 36.0) * (T(3) * (eF - uF) + T(9) * eu * eF);
-            C = (a < 11) ? Cxy : ((a < 15) ? Cxz : Cyz);
-        }
-        f[a] = f[a] - omega * (f[a] - feq) + om2 * (G + C);
-    }
+    // axis pairs: w = 1/18, php coefficient -1;  edge pairs: w = 1/36, +1/4
+    const T Ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
+    const T Ue = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
+    const T oa = T(3) * r18 - php, oe = T(3) * r36 + T(0.25) * php;
+    const T wa45 = T(4.5) * r18, we45 = T(4.5) * r36;
+    const T ga = T(-3.0 / 18.0) * uF, ge = T(-3.0 / 36.0) * uF;
+    const T a9 = T(0.5), a3 = T(1.0 / 6.0), e9 = T(0.25), e3 = T(1.0 / 12.0);
+    pair_update<T>(f[1], f[2], ux, Fx, Ua, wa45, oa, a9, a3, ga, Cx, omega, om1, om2);
+    pair_update<T>(f[3], f[4], uy, Fy, Ua, wa45, oa, a9, a3, ga, Cy, omega, om1, om2);
+    pair_update<T>(f[5], f[6], uz, Fz, Ua, wa45, oa, a9, a3, ga, Cz, omega, om1, om2);
+    pair_update<T>(f[7], f[8], ux + uy, Fx + Fy, Ue, we45, oe, e9, e3, ge, Cxy, omega, om1, om2);
+    pair_update<T>(f[9], f[10], ux - uy, Fx - Fy, Ue, we45, oe, e9, e3, ge, Cxy, omega, om1, om2);
+    pair_update<T>(f[11], f[12], ux + uz, Fx + Fz, Ue, we45, oe, e9, e3, ge, Cxz, omega, om1, om2);
+    pair_update<T>(f[13], f[14], ux - uz, Fx - Fz, Ue, we45, oe, e9, e3, ge, Cxz, omega, om1, om2);
+    pair_update<T>(f[15], f[16], uy + uz, Fy + Fz, Ue, we45, oe, e9, e3, ge, Cyz, omega, om1, om2);
+    pair_update<T>(f[17], f[18], uy - uz, Fy - Fz, Ue, we45, oe, e9, e3, ge, Cyz, omega, om1, om2);
 }
 
 template <typename T>
@@ -170,7 +168,8 @@ __device__ __forceinline__ void equilibrium(T feq[19], T rho, T drho, T ux, T uy
 //   C  F and u (and psi = phi u, improved) of slice za - 2
 //   D  collide and store slice za - 3 (the thread's own populations, pulled
 //      three iterations earlier, wait in a register FIFO when FIFO is set)
-// Rings hold 4 slices (slot = (z - z0 + 8) & 3); F and u of the tile hold 2.
+// rho is kept for 4 slices (slot (z - z0 + 8) & 3); mu, j, psi and P for 3
+// (slot (z - z0 + 9) % 3); F and u of the tile for 2.
 template <typename S, typename T, int V, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
@@ -181,9 +180,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr bool PT = (V == kStdPtensor);
     constexpr bool FIFO = sizeof(T) == 4;       // float64 re-reads its populations in stage D instead
     __shared__ T s_rho[4 * A3];
-    __shared__ T s_mu[4 * A2];
-    __shared__ T s_j[3 * 4 * A1];
-    __shared__ T s_psi[IMP ? 3 * 4 * A1 : 1];
+    __shared__ T s_mu[3 * A2];
+    __shared__ T s_j[3 * 3 * A1];               // component stride 3 * A1
+    __shared__ T s_psi[IMP ? 3 * 3 * A1 : 1];
     __shared__ T s_P[PT ? 4 * 3 * A2 : 1];      // p, d_x rho, d_y rho, d_z rho; ring of 3 slices
     __shared__ T s_fu[6 * 2 * NT];              // Fx Fy Fz ux uy uz of the tile, 2 slices
     __shared__ double s_red[7 * (NT / 64)];
@@ -205,6 +204,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const int sx = R.slow_x, sy = R.slow_y, sz = R.slow_z;
     const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + R.state_offset * 19;
     S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + R.state_offset * 19;
+    const S* pp[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
     const T rho_ref = (T)R.rho_ref, mu_ref = (T)R.mu_ref;
@@ -231,16 +233,17 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) Z[k] = wrap(za - 1 + k, nz, sz) * NXY;
         const int slA = (za - z0 + 8) & 3;
+        const int slA3 = (za - z0 + 9) % 3;
 
         // ---- A: interior column of this thread ----
         {
             T f[19];
-            pull<S, T>(src, N, OX, OY, Z, f);
+            pull<S, T>(pp, OX, OY, Z, f);
             s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum19(f);
             T jx, jy, jz;
             mom19(f, jx, jy, jz);
-            const int c1 = slA * A1 + (ly0 + 1) * W1 + lx0 + 1;
-            s_j[c1] = jx; s_j[4 * A1 + c1] = jy; s_j[8 * A1 + c1] = jz;
+            const int c1 = slA3 * A1 + (ly0 + 1) * W1 + lx0 + 1;
+            s_j[c1] = jx; s_j[3 * A1 + c1] = jy; s_j[6 * A1 + c1] = jz;
             if constexpr (FIFO) {
 #pragma unroll
                 for (int a = 0; a < 19; ++a) fifo[3][a] = f[a];
@@ -268,13 +271,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 Y[q] = wrap(hy - 1 + q, ny, sy) * nx;
             }
             T f[19];
-            pull<S, T>(src, N, X, Y, Z, f);
+            pull<S, T>(pp, X, Y, Z, f);
             s_rho[slA * A3 + ly * W3 + lx] = rho_ref + sum19(f);
             if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
                 T jx, jy, jz;
                 mom19(f, jx, jy, jz);
-                const int c1 = slA * A1 + (ly - 2) * W1 + lx - 2;
-                s_j[c1] = jx; s_j[4 * A1 + c1] = jy; s_j[8 * A1 + c1] = jz;
+                const int c1 = slA3 * A1 + (ly - 2) * W1 + lx - 2;
+                s_j[c1] = jx; s_j[3 * A1 + c1] = jy; s_j[6 * A1 + c1] = jz;
             }
         }
         __syncthreads();
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             const T* Rd = s_rho + ((zb - 1 - z0 + 8) & 3) * A3;
             const T* Rp = s_rho + ((zb - z0 + 8) & 3) * A3;
             const T* Ru = s_rho + ((zb + 1 - z0 + 8) & 3) * A3;
-            const int slB = (zb - z0 + 8) & 3;
+            const int slB = (zb - z0 + 9) % 3;
             for (int k = tid; k < A2; k += NT) {
                 const int lx = k % W2, ly = k / W2;
                 const int c = (ly + 1) * W3 + lx + 1;
@@ -310,6 +313,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         if (it >= 4) {
             const int zc = za - 2;
             const int sd = (zc - 1 - z0 + 8) & 3, sp = (zc - z0 + 8) & 3, su = (zc + 1 - z0 + 8) & 3;
+            const int md = (zc - 1 - z0 + 9) % 3, mp = (zc - z0 + 9) % 3, mu3 = (zc + 1 - z0 + 9) % 3;
             const int sfu = (zc - z0 + 8) & 1;
             constexpr int NC = IMP ? A1 : NT;          // improved needs psi on tile + 1
             for (int k = tid; k < NC; k += NT) {
@@ -319,9 +323,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 const int c3 = (ly + 2) * W3 + lx + 2;
                 const T r = s_rho[sp * A3 + c3];
                 T Fx, Fy, Fz;
-                const T* Md = s_mu + sd * A2;
-                const T* Mp = s_mu + sp * A2;
-                const T* Mu = s_mu + su * A2;
+                const T* Md = s_mu + md * A2;
+                const T* Mp = s_mu + mp * A2;
+                const T* Mu = s_mu + mu3 * A2;
                 if constexpr (IMP) {
                     const T g = T(1.0 / 3.0) - r;                                       // Eq. 24
                     Fx = g * gx<W2>(Md, Mp, Mu, c2);
@@ -355,16 +359,16 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                         Fz = az - r * gz<W2>(Md, Mp, Mu, c2);
                     }
                 }
-                const int c1 = sp * A1 + ly * W1 + lx;
+                const int c1 = mp * A1 + ly * W1 + lx;
                 const T ir = T(1) / r;
                 const T ux = (s_j[c1] + T(0.5) * Fx) * ir;
-                const T uy = (s_j[4 * A1 + c1] + T(0.5) * Fy) * ir;
-                const T uz = (s_j[8 * A1 + c1] + T(0.5) * Fz) * ir;
+                const T uy = (s_j[3 * A1 + c1] + T(0.5) * Fy) * ir;
+                const T uz = (s_j[6 * A1 + c1] + T(0.5) * Fz) * ir;
                 if constexpr (IMP) {
                     const T phi = r * T(1.0 / 3.0) - (T(1) + Mp[c2]) * T(1.0 / 3.0);    // Eq. 29
                     s_psi[c1] = phi * ux;
-                    s_psi[4 * A1 + c1] = phi * uy;
-                    s_psi[8 * A1 + c1] = phi * uz;
+                    s_psi[3 * A1 + c1] = phi * uy;
+                    s_psi[6 * A1 + c1] = phi * uz;
                 }
                 if (lx >= 1 && lx <= BX && ly >= 1 && ly <= BY) {
                     T* fu = s_fu + sfu * 6 * NT + (ly - 1) * BX + lx - 1;
@@ -378,10 +382,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         // ---- D: collide and store slice za - 3 ----
         if (it >= 6 && own_valid) {
             const int zd = za - 3;
-            const int sd = (zd - 1 - z0 + 8) & 3, sp = (zd - z0 + 8) & 3, su = (zd + 1 - z0 + 8) & 3;
+            const int sp = (zd - z0 + 8) & 3;
+            const int md = (zd - 1 - z0 + 9) % 3, mp = (zd - z0 + 9) % 3, mu3 = (zd + 1 - z0 + 9) % 3;
             const int sfu = (zd - z0 + 8) & 1;
             const T r = s_rho[sp * A3 + (ly0 + 3) * W3 + lx0 + 3];
-            const T mu = s_mu[sp * A2 + (ly0 + 2) * W2 + lx0 + 2];
+            const T mu = s_mu[mp * A2 + (ly0 + 2) * W2 + lx0 + 2];
             const T* fu = s_fu + sfu * 6 * NT + tid;
             const T Fx = fu[0], Fy = fu[NT], Fz = fu[2 * NT], ux = fu[3 * NT], uy = fu[4 * NT], uz = fu[5 * NT];
             T f[19];
@@ -392,7 +397,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 int Zd[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) Zd[k] = wrap(zd - 1 + k, nz, sz) * NXY;
-                pull<S, T>(src, N, OX, OY, Zd, f);
+                pull<S, T>(pp, OX, OY, Zd, f);
             }
             const T drho = sum19(f);
             const int node = zd * NXY + gy0 * nx + gx0;
@@ -409,9 +414,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 T dpm, php, Cxx = T(0), Cyy = T(0), Czz = T(0);
                 if constexpr (IMP) {
                     const int c1 = (ly0 + 1) * W1 + lx0 + 1;
-                    const T* Xd = s_psi + sd * A1; const T* Xp = s_psi + sp * A1; const T* Xu = s_psi + su * A1;
-                    const T* Yd = Xd + 4 * A1; const T* Yp = Xp + 4 * A1; const T* Yu = Xu + 4 * A1;
-                    const T* Zdd = Xd + 8 * A1; const T* Zp = Xp + 8 * A1; const T* Zu = Xu + 8 * A1;
+                    const T* Xd = s_psi + md * A1; const T* Xp = s_psi + mp * A1; const T* Xu = s_psi + mu3 * A1;
+                    const T* Yd = Xd + 3 * A1; const T* Yp = Xp + 3 * A1; const T* Yu = Xu + 3 * A1;
+                    const T* Zdd = Xd + 6 * A1; const T* Zp = Xp + 6 * A1; const T* Zu = Xu + 6 * A1;
                     Cxx = T(3) * gx<W1>(Xd, Xp, Xu, c1);
                     Cyy = T(3) * gy<W1>(Yd, Yp, Yu, c1);
                     Czz = T(3) * gz<W1>(Zdd, Zp, Zu, c1);
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 }
                 collide<T>(f, r, drho, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
 #pragma unroll
-                for (int a = 0; a < 19; ++a) dst[a * N + node] = (S)f[a];
+                for (int a = 0; a < 19; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
             }
             acc.mass += (double)drho;
             acc.mx += (double)(r * ux);
@@ -534,6 +539,9 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 namespace {
 template <typename S, typename T, int V, int BX, int BY>
 hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
+    if constexpr (sizeof(T) == 8 && BX * BY > 256) {
+        return hipErrorInvalidValue;      // float64 rings of this tile exceed the 160 KB of LDS
+    } else {
     if (mode == kFields)
         hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kFields>), dim3(grid), dim3(BX * BY), 0, s, a);
     else if (mode == kStepDiag)
@@ -541,22 +549,24 @@ hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
     else
         hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep>), dim3(grid), dim3(BX * BY), 0, s, a);
     return hipGetLastError();
+    }
 }
 template <typename S, typename T, int V>
 hipError_t launch3_shape(const StepArgs& a, int grid, hipStream_t s, int fields, int shape) {
     switch (shape) {
         case 0: return launch3_t<S, T, V, 32, 8>(a, grid, s, fields);
-        case 1: return launch3_t<S, T, V, 16, 16>(a, grid, s, fields);
-        case 2: return launch3_t<S, T, V, 64, 4>(a, grid, s, fields);
+        case 1: return launch3_t<S, T, V, 32, 16>(a, grid, s, fields);
+        case 2: return launch3_t<S, T, V, 16, 16>(a, grid, s, fields);
+        case 3: return launch3_t<S, T, V, 64, 4>(a, grid, s, fields);
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
 extern const int kD3Q19Shapes[][2];
-const int kD3Q19Shapes[][2] = {{32, 8}, {16, 16}, {64, 4}};
+const int kD3Q19Shapes[][2] = {{32, 8}, {32, 16}, {16, 16}, {64, 4}};
 extern const int kNumD3Q19Shapes;
-const int kNumD3Q19Shapes = 3;
+const int kNumD3Q19Shapes = 4;
 
 hipError_t d3q19_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
                              int fields) {

@@ -14,6 +14,17 @@ __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ bool dev_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool dev_finite(double x) { return isfinite(x); }
 
+// Load / store at a wave-uniform base plus a 32-bit byte offset, the form the
+// hardware takes with the base in scalar registers (no 64-bit lane addresses).
+template <typename S>
+__device__ __forceinline__ S ld_off(const S* base, unsigned idx) {
+    return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ void st_off(S* base, unsigned idx, S v) {
+    *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(S)) = v;
+}
+
 // Periodic wrap of a coordinate that is at most a few nodes outside [0, n).
 // `slow` is set by the host when n is too small for one conditional correction.
 __device__ __forceinline__ int wrap(int v, int n, int slow) {
@@ -113,6 +124,24 @@ __device__ __forceinline__ void block_reduce_store(const DiagAcc& a, DiagPartial
         }
         *out = p;
     }
+}
+
+// BGK update of a pair of opposite velocities e and -e (same weight w):
+//   f*_(+-) = (1 - omega) f_(+-) + omega feq_(+-) + (1 - omega/2) (G_(+-) + C),
+// with feq_(+-) = U + 4.5 w rho eu^2 +- (3 w rho + k php) eu  (even +- odd part) and
+// G_(+-) = w (9 eu eF - 3 u.F) +- 3 w eF  (Eq. 14 split the same way).
+// U holds the u-independent part and -1.5 w rho u^2; C is even.
+template <typename T>
+__device__ __forceinline__ void pair_update(T& fp, T& fm, T eu, T eF, T U, T w45r, T oddc, T w9, T w3, T mw3uF,
+                                            T C, T omega, T om1, T om2) {
+    const T s = U + w45r * eu * eu;
+    const T o = oddc * eu;
+    const T Ge = w9 * eu * eF + mw3uF;
+    const T Go = w3 * eF;
+    const T E = omega * s + om2 * (Ge + C);
+    const T O = omega * o + om2 * Go;
+    fp = om1 * fp + E + O;
+    fm = om1 * fm + E - O;
 }
 
 template <typename T>
