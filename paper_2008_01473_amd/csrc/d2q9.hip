@@ -94,14 +94,16 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
     // axis pairs: w = 1/9, php coefficient -1/2;  diagonal pairs: w = 1/36, +1/4
     const T Ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
     const T Ud = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
-    const T oa = T(3) * r9 - T(0.5) * php, od = T(3) * r36 + T(0.25) * php;
-    const T ga = T(-3.0 / 9.0) * uF, gd = T(-3.0 / 36.0) * uF;
-    pair_update<T>(f[1], f[3], ux, Fx, Ua, T(4.5) * r9, oa, T(1.0), T(1.0 / 3.0), ga, Ca, omega, om1, om2);
-    pair_update<T>(f[2], f[4], uy, Fy, Ua, T(4.5) * r9, oa, T(1.0), T(1.0 / 3.0), ga, Cb, omega, om1, om2);
-    pair_update<T>(f[5], f[7], ux + uy, Fx + Fy, Ud, T(4.5) * r36, od, T(0.25), T(1.0 / 12.0), gd, Cd, omega, om1,
-                   om2);
-    pair_update<T>(f[6], f[8], uy - ux, Fy - Fx, Ud, T(4.5) * r36, od, T(0.25), T(1.0 / 12.0), gd, Cd, omega, om1,
-                   om2);
+    const T ea = omega * Ua - om2 * T(3.0 / 9.0) * uF, ed = omega * Ud - om2 * T(3.0 / 36.0) * uF;
+    const T e1a = omega * T(4.5) * r9, e1d = omega * T(4.5) * r36;
+    const T e2a = om2 * T(1.0), e2d = om2 * T(0.25);
+    const T o1a = omega * (T(3) * r9 - T(0.5) * php), o1d = omega * (T(3) * r36 + T(0.25) * php);
+    const T o2a = om2 * T(1.0 / 3.0), o2d = om2 * T(1.0 / 12.0);
+    pair_update<T>(f[1], f[3], ux, Fx, ea + om2 * Ca, e1a, e2a, o1a, o2a, om1);
+    pair_update<T>(f[2], f[4], uy, Fy, ea + om2 * Cb, e1a, e2a, o1a, o2a, om1);
+    const T ed2 = ed + om2 * Cd;
+    pair_update<T>(f[5], f[7], ux + uy, Fx + Fy, ed2, e1d, e2d, o1d, o2d, om1);
+    pair_update<T>(f[6], f[8], uy - ux, Fy - Fx, ed2, e1d, e2d, o1d, o2d, om1);
 }
 
 // Equilibrium minus reference for initialisation (same closed forms, no force).
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             Fx = ddx<W3>(s_rho, c3) * T(1.0 / 3.0) - r * ddx<W2>(s_mu, c2);
             Fy = ddy<W3>(s_rho, c3) * T(1.0 / 3.0) - r * ddy<W2>(s_mu, c2);
         }
-        const T ir = T(1) / r;
+        const T ir = dev_rcp(r);
         const T ux = (s_a[k] + T(0.5) * Fx) * ir;
         const T uy = (s_b[k] + T(0.5) * Fy) * ir;
         if constexpr (IMP) {

@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 #include "lbm_shared.hpp"
 
@@ -131,19 +133,21 @@ __device__ __forceinline__ void collide(T f[19], T rho, T drho, T ux, T uy, T uz
     // axis pairs: w = 1/18, php coefficient -1;  edge pairs: w = 1/36, +1/4
     const T Ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
     const T Ue = dpm * T(1.0 / 12.0) - T(1.5) * r36 * usq;
-    const T oa = T(3) * r18 - php, oe = T(3) * r36 + T(0.25) * php;
-    const T wa45 = T(4.5) * r18, we45 = T(4.5) * r36;
-    const T ga = T(-3.0 / 18.0) * uF, ge = T(-3.0 / 36.0) * uF;
-    const T a9 = T(0.5), a3 = T(1.0 / 6.0), e9 = T(0.25), e3 = T(1.0 / 12.0);
-    pair_update<T>(f[1], f[2], ux, Fx, Ua, wa45, oa, a9, a3, ga, Cx, omega, om1, om2);
-    pair_update<T>(f[3], f[4], uy, Fy, Ua, wa45, oa, a9, a3, ga, Cy, omega, om1, om2);
-    pair_update<T>(f[5], f[6], uz, Fz, Ua, wa45, oa, a9, a3, ga, Cz, omega, om1, om2);
-    pair_update<T>(f[7], f[8], ux + uy, Fx + Fy, Ue, we45, oe, e9, e3, ge, Cxy, omega, om1, om2);
-    pair_update<T>(f[9], f[10], ux - uy, Fx - Fy, Ue, we45, oe, e9, e3, ge, Cxy, omega, om1, om2);
-    pair_update<T>(f[11], f[12], ux + uz, Fx + Fz, Ue, we45, oe, e9, e3, ge, Cxz, omega, om1, om2);
-    pair_update<T>(f[13], f[14], ux - uz, Fx - Fz, Ue, we45, oe, e9, e3, ge, Cxz, omega, om1, om2);
-    pair_update<T>(f[15], f[16], uy + uz, Fy + Fz, Ue, we45, oe, e9, e3, ge, Cyz, omega, om1, om2);
-    pair_update<T>(f[17], f[18], uy - uz, Fy - Fz, Ue, we45, oe, e9, e3, ge, Cyz, omega, om1, om2);
+    const T ea = omega * Ua - om2 * T(3.0 / 18.0) * uF, ee = omega * Ue - om2 * T(3.0 / 36.0) * uF;
+    const T e1a = omega * T(4.5) * r18, e1e = omega * T(4.5) * r36;
+    const T e2a = om2 * T(0.5), e2e = om2 * T(0.25);
+    const T o1a = omega * (T(3) * r18 - php), o1e = omega * (T(3) * r36 + T(0.25) * php);
+    const T o2a = om2 * T(1.0 / 6.0), o2e = om2 * T(1.0 / 12.0);
+    pair_update<T>(f[1], f[2], ux, Fx, ea + om2 * Cx, e1a, e2a, o1a, o2a, om1);
+    pair_update<T>(f[3], f[4], uy, Fy, ea + om2 * Cy, e1a, e2a, o1a, o2a, om1);
+    pair_update<T>(f[5], f[6], uz, Fz, ea + om2 * Cz, e1a, e2a, o1a, o2a, om1);
+    const T exy = ee + om2 * Cxy, exz = ee + om2 * Cxz, eyz = ee + om2 * Cyz;
+    pair_update<T>(f[7], f[8], ux + uy, Fx + Fy, exy, e1e, e2e, o1e, o2e, om1);
+    pair_update<T>(f[9], f[10], ux - uy, Fx - Fy, exy, e1e, e2e, o1e, o2e, om1);
+    pair_update<T>(f[11], f[12], ux + uz, Fx + Fz, exz, e1e, e2e, o1e, o2e, om1);
+    pair_update<T>(f[13], f[14], ux - uz, Fx - Fz, exz, e1e, e2e, o1e, o2e, om1);
+    pair_update<T>(f[15], f[16], uy + uz, Fy + Fz, eyz, e1e, e2e, o1e, o2e, om1);
+    pair_update<T>(f[17], f[18], uy - uz, Fy - Fz, eyz, e1e, e2e, o1e, o2e, om1);
 }
 
 template <typename T>
@@ -227,7 +231,45 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     T fifo[FIFO ? 4 : 1][19];
     DiagAcc acc;
 
-    for (int it = 0; it < zn + 6; ++it) {
+    // Halo nodes of stage A handled by this thread: their in-slice position and
+    // wrapped x / y neighbour offsets do not change along the sweep, so they are
+    // decoded once here (idle lanes repeat the last halo node and store nothing).
+    constexpr int HALO = A3 - NT;
+    constexpr int HP = (HALO + NT - 1) / NT;
+    int hX[HP][3], hY[HP][3], hpos[HP], hpos1[HP];
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+        int k = tid + q * NT;
+        k = k < HALO ? k : HALO - 1;
+        int lx, ly;
+        if (k < 3 * W3) {
+            ly = k / W3; lx = k % W3;
+        } else if (k < 6 * W3) {
+            const int k2 = k - 3 * W3;
+            ly = H3 - 3 + k2 / W3; lx = k2 % W3;
+        } else {
+            const int k3 = k - 6 * W3;
+            ly = 3 + k3 / 6;
+            const int c = k3 % 6;
+            lx = c < 3 ? c : W3 - 6 + c;
+        }
+        const int hx = x0 - 3 + lx, hy = y0 - 3 + ly;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            hX[q][d] = wrap(hx - 1 + d, nx, sx);
+            hY[q][d] = wrap(hy - 1 + d, ny, sy) * nx;
+        }
+        hpos[q] = (tid + q * NT < HALO) ? ly * W3 + lx : -1;
+        hpos1[q] = (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) ? (ly - 2) * W1 + lx - 2 : -1;
+    }
+
+    // The sweep is unrolled by four so that the FIFO slot written by stage A
+    // (it mod 4) and the one read by stage D (three iterations later) are
+    // compile-time register names.  Iterations past NIT only pass the barriers.
+    const int NIT = zn + 6;
+    auto iteration = [&](const int it, auto slot) {
+        constexpr int KW = decltype(slot)::value;
+        constexpr int KR = (KW + 1) & 3;
         const int za = z0 - 3 + it;
         int Z[3];
 #pragma unroll
@@ -235,10 +277,14 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int slA = (za - z0 + 8) & 3;
         const int slA3 = (za - z0 + 9) % 3;
 
-        // ---- A: interior column of this thread ----
-        {
+        // ---- A: interior column of this thread, then its halo nodes; all loads
+        // are issued before any is used ----
+        if (it < NIT) {
             T f[19];
+            T fh[HP][19];
             pull<S, T>(pp, OX, OY, Z, f);
+#pragma unroll
+            for (int q = 0; q < HP; ++q) pull<S, T>(pp, hX[q], hY[q], Z, fh[q]);
             s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum19(f);
             T jx, jy, jz;
             mom19(f, jx, jy, jz);
@@ -246,44 +292,25 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             s_j[c1] = jx; s_j[3 * A1 + c1] = jy; s_j[6 * A1 + c1] = jz;
             if constexpr (FIFO) {
 #pragma unroll
-                for (int a = 0; a < 19; ++a) fifo[3][a] = f[a];
+                for (int a = 0; a < 19; ++a) fifo[KW][a] = f[a];
             }
-        }
-        // ---- A: halo rings of the slice ----
-        for (int k = tid; k < A3 - NT; k += NT) {
-            int lx, ly;
-            if (k < 3 * W3) {
-                ly = k / W3; lx = k % W3;
-            } else if (k < 6 * W3) {
-                const int k2 = k - 3 * W3;
-                ly = H3 - 3 + k2 / W3; lx = k2 % W3;
-            } else {
-                const int k3 = k - 6 * W3;
-                ly = 3 + k3 / 6;
-                const int c = k3 % 6;
-                lx = c < 3 ? c : W3 - 6 + c;
-            }
-            const int hx = x0 - 3 + lx, hy = y0 - 3 + ly;
-            int X[3], Y[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                X[q] = wrap(hx - 1 + q, nx, sx);
-                Y[q] = wrap(hy - 1 + q, ny, sy) * nx;
-            }
-            T f[19];
-            pull<S, T>(pp, X, Y, Z, f);
-            s_rho[slA * A3 + ly * W3 + lx] = rho_ref + sum19(f);
-            if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
-                T jx, jy, jz;
-                mom19(f, jx, jy, jz);
-                const int c1 = slA3 * A1 + (ly - 2) * W1 + lx - 2;
-                s_j[c1] = jx; s_j[3 * A1 + c1] = jy; s_j[6 * A1 + c1] = jz;
+            for (int q = 0; q < HP; ++q) {
+                if (hpos[q] >= 0) {
+                    s_rho[slA * A3 + hpos[q]] = rho_ref + sum19(fh[q]);
+                    if (hpos1[q] >= 0) {
+                        T hx_, hy_, hz_;
+                        mom19(fh[q], hx_, hy_, hz_);
+                        const int h1 = slA3 * A1 + hpos1[q];
+                        s_j[h1] = hx_; s_j[3 * A1 + h1] = hy_; s_j[6 * A1 + h1] = hz_;
+                    }
+                }
             }
         }
         __syncthreads();
 
         // ---- B: mu (and P) of slice za - 1 on tile + 2 ----
-        if (it >= 2) {
+        if (it >= 2 && it < NIT) {
             const int zb = za - 1;
             const T* Rd = s_rho + ((zb - 1 - z0 + 8) & 3) * A3;
             const T* Rp = s_rho + ((zb - z0 + 8) & 3) * A3;
@@ -310,7 +337,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         __syncthreads();
 
         // ---- C: F, u (and psi) of slice za - 2 ----
-        if (it >= 4) {
+        if (it >= 4 && it < NIT) {
             const int zc = za - 2;
             const int sd = (zc - 1 - z0 + 8) & 3, sp = (zc - z0 + 8) & 3, su = (zc + 1 - z0 + 8) & 3;
             const int md = (zc - 1 - z0 + 9) % 3, mp = (zc - z0 + 9) % 3, mu3 = (zc + 1 - z0 + 9) % 3;
@@ -360,7 +387,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     }
                 }
                 const int c1 = mp * A1 + ly * W1 + lx;
-                const T ir = T(1) / r;
+                const T ir = dev_rcp(r);
                 const T ux = (s_j[c1] + T(0.5) * Fx) * ir;
                 const T uy = (s_j[3 * A1 + c1] + T(0.5) * Fy) * ir;
                 const T uz = (s_j[6 * A1 + c1] + T(0.5) * Fz) * ir;
@@ -380,7 +407,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         __syncthreads();
 
         // ---- D: collide and store slice za - 3 ----
-        if (it >= 6 && own_valid) {
+        if (it >= 6 && it < NIT && own_valid) {
             const int zd = za - 3;
             const int sp = (zd - z0 + 8) & 3;
             const int md = (zd - 1 - z0 + 9) % 3, mp = (zd - z0 + 9) % 3, mu3 = (zd + 1 - z0 + 9) % 3;
@@ -392,7 +419,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             T f[19];
             if constexpr (FIFO) {
 #pragma unroll
-                for (int a = 0; a < 19; ++a) f[a] = fifo[0][a];
+                for (int a = 0; a < 19; ++a) f[a] = fifo[KR][a];
             } else {
                 int Zd[3];
 #pragma unroll
@@ -439,15 +466,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             acc.mumax = fmax(acc.mumax, (double)mu);
             acc.status |= blowup_bits<T>(r, ux, uy, uz, R.rho_max);
         }
-        if constexpr (FIFO) {
-#pragma unroll
-            for (int a = 0; a < 19; ++a) {
-                fifo[0][a] = fifo[1][a];
-                fifo[1][a] = fifo[2][a];
-                fifo[2][a] = fifo[3][a];
-            }
-        }
         __syncthreads();
+    };
+    for (int it0 = 0; it0 < NIT; it0 += 4) {
+        iteration(it0, std::integral_constant<int, 0>{});
+        iteration(it0 + 1, std::integral_constant<int, 1>{});
+        iteration(it0 + 2, std::integral_constant<int, 2>{});
+        iteration(it0 + 3, std::integral_constant<int, 3>{});
     }
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + tile.lat, acc.status);

@@ -14,6 +14,13 @@ __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ bool dev_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool dev_finite(double x) { return isfinite(x); }
 
+// Reciprocal and logarithm on the step's critical path: exact (IEEE) in float64;
+// the hardware 1-ulp instructions in float32.
+__device__ __forceinline__ double dev_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double dev_logf(double x) { return log(x); }
+__device__ __forceinline__ float dev_logf(float x) { return __logf(x); }
+
 // Load / store at a wave-uniform base plus a 32-bit byte offset, the form the
 // hardware takes with the base in scalar registers (no 64-bit lane addresses).
 template <typename S>
@@ -45,16 +52,7 @@ struct Eos {
     int kind;
     T a, b, RT;
 
-    __device__ __forceinline__ T mu(T rho) const {
-        if (kind == 0) {
-            const T ibr = T(1) / (T(1) - b * rho);
-            return RT * (dev_log(rho * ibr) + ibr) - T(2) * a * rho;
-        }
-        const T h = T(0.25) * b * rho;
-        const T iom = T(1) / (T(1) - h);
-        const T iom3 = iom * iom * iom;
-        return RT * (dev_log(rho) + T(1) + h * (T(8) - T(9) * h + T(3) * h * h) * iom3) - T(2) * a * rho;
-    }
+    __device__ __forceinline__ T mu(T rho) const;
 
     __device__ __forceinline__ T p(T rho) const {
         if (kind == 0) return rho * RT / (T(1) - b * rho) - a * rho * rho;
@@ -63,6 +61,18 @@ struct Eos {
         return rho * RT * (T(1) + h + h * h - h * h * h) * (iom * iom * iom) - a * rho * rho;
     }
 };
+
+template <typename T>
+__device__ __forceinline__ T Eos<T>::mu(T rho) const {
+    if (kind == 0) {
+        const T ibr = dev_rcp(T(1) - b * rho);
+        return RT * (dev_logf(rho * ibr) + ibr) - T(2) * a * rho;
+    }
+    const T h = T(0.25) * b * rho;
+    const T iom = dev_rcp(T(1) - h);
+    const T iom3 = iom * iom * iom;
+    return RT * (dev_logf(rho) + T(1) + h * (T(8) - T(9) * h + T(3) * h * h) * iom3) - T(2) * a * rho;
+}
 
 // Block -> tile mapping that keeps spatially adjacent tiles on one XCD: work
 // groups are dealt to the 8 XCDs round-robin, so block b runs on XCD b % 8 and
@@ -129,19 +139,17 @@ __device__ __forceinline__ void block_reduce_store(const DiagAcc& a, DiagPartial
 // BGK update of a pair of opposite velocities e and -e (same weight w):
 //   f*_(+-) = (1 - omega) f_(+-) + omega feq_(+-) + (1 - omega/2) (G_(+-) + C),
 // with feq_(+-) = U + 4.5 w rho eu^2 +- (3 w rho + k php) eu  (even +- odd part) and
-// G_(+-) = w (9 eu eF - 3 u.F) +- 3 w eF  (Eq. 14 split the same way).
-// U holds the u-independent part and -1.5 w rho u^2; C is even.
+// G_(+-) = w (9 eu eF - 3 u.F) +- 3 w eF  (Eq. 14 split the same way); U holds the
+// u-independent part and -1.5 w rho u^2, C is even.  With the relaxation folded
+// into per-class coefficients the even and odd parts are
+//   E = e0 + eu (e1 eu + e2 eF),  e0 = omega U + om2 (C - 3 w u.F), e1 = 4.5 omega w rho, e2 = 9 om2 w
+//   O = o1 eu + o2 eF,            o1 = omega (3 w rho + k php),        o2 = 3 om2 w
 template <typename T>
-__device__ __forceinline__ void pair_update(T& fp, T& fm, T eu, T eF, T U, T w45r, T oddc, T w9, T w3, T mw3uF,
-                                            T C, T omega, T om1, T om2) {
-    const T s = U + w45r * eu * eu;
-    const T o = oddc * eu;
-    const T Ge = w9 * eu * eF + mw3uF;
-    const T Go = w3 * eF;
-    const T E = omega * s + om2 * (Ge + C);
-    const T O = omega * o + om2 * Go;
-    fp = om1 * fp + E + O;
-    fm = om1 * fm + E - O;
+__device__ __forceinline__ void pair_update(T& fp, T& fm, T eu, T eF, T e0, T e1, T e2, T o1, T o2, T om1) {
+    const T E = e0 + eu * (e1 * eu + e2 * eF);
+    const T O = o1 * eu + o2 * eF;
+    fp = om1 * fp + (E + O);
+    fm = om1 * fm + (E - O);
 }
 
 template <typename T>
