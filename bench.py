@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graphs", action="store_true", help="one kernel launch per step (for counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape (no autotuning)")
+    ap.add_argument("--tile", type=int, default=-1, help="force this tile-shape index (no autotuning)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run the plain copy kernel on this many MiB, 5 times (traffic-counter calibration)")
     return ap.parse_args()
@@ -63,13 +64,15 @@ def timed_steps(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True, tune=0):
+def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True, tune=0, tile=-1):
     """Build one workload, time it, return a result record."""
     p_list, rho0 = spec["params"], spec["rho0"]
     sim = runtime.LBM(p_list)
     sim.use_graphs(graphs)
     sim.init(rho0)
-    if tune:
+    if tile >= 0:
+        sim.set_tile_shape(tile)
+    elif tune:
         sim.autotune(tune)          # times every tile shape on this state, keeps the fastest
     shape = sim.tile_shape()
     ms = timed_steps(torch, sim, steps, warmup)
@@ -106,6 +109,18 @@ def primary_spec(runtime, inputs, precision="fp64", scheme="improved", T=0.8):
     return {"name": f"d2q9_512_cs_{scheme}_{precision}", "params": [p], "rho0": rho0,
             "workload": f"D2Q9 512x512 periodic, Carnahan-Starling droplet r=80 W=5, T/Tc={T}, kappa=0.01, "
                         f"tau=0.8, {scheme} scheme, {precision}"}
+
+
+def d2q9_large_spec(runtime, inputs, precision="fp64", n=4096):
+    """The primary's physics on a lattice large enough to leave the launch-latency
+    regime: n x n CS droplet of radius 80 n / 512."""
+    m = runtime.maxwell("CS", 0.8)
+    p = runtime.params("D2Q9", n, n, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8, scheme="improved",
+                       precision=precision)
+    rho0 = inputs.droplet((n, n), m["rho_g"], m["rho_l"], 80.0 * n / 512, 5.0, noise=0.0)
+    return {"name": f"d2q9_{n}_cs_improved_{precision}", "params": [p], "rho0": rho0,
+            "workload": f"D2Q9 {n}x{n} periodic, CS droplet r={80 * n // 512}, T/Tc=0.8, kappa=0.01, tau=0.8, "
+                        f"improved, {precision}"}
 
 
 def d3q19_spec(runtime, inputs, T=0.8):
@@ -226,7 +241,8 @@ def main():
         return
     graphs = not args.no_graphs
     tune = 0 if args.no_tune else 20
-    prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs, tune)
+    prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs, tune,
+                   args.tile)
     print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step",
           file=sys.stderr, flush=True)
     secondary = []
@@ -237,6 +253,8 @@ def main():
             # the standard scheme blows up for this droplet at T/Tc = 0.8 (oracle too); 0.9 is stable
             ("standard", lambda: primary_spec(runtime, inputs, scheme="standard", T=0.9), args.steps),
             ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),
+            ("d2q9_4096_fp64", lambda: d2q9_large_spec(runtime, inputs, "fp64"), max(20, args.steps // 40)),
+            ("d2q9_4096_fp32", lambda: d2q9_large_spec(runtime, inputs, "fp32"), max(20, args.steps // 40)),
             ("batch", lambda: batch_spec(runtime, inputs), max(20, args.steps // 20)),
         ]
         if not only or "adjoint" in only:
@@ -248,7 +266,11 @@ def main():
         for name, mk, k in jobs:
             if only and name not in only:
                 continue
-            r = measure(torch, runtime, inputs, mk(), k, min(args.warmup, k), graphs, tune)
+            try:
+                r = measure(torch, runtime, inputs, mk(), k, min(args.warmup, k), graphs, tune, args.tile)
+            except runtime._lib.LBMError as e:        # a forced tile shape this workload does not support
+                print(f"[bench] {name}: skipped ({e})", file=sys.stderr, flush=True)
+                continue
             r["steps"] = k
             r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
             secondary.append(r)

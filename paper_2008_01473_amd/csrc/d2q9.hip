@@ -432,15 +432,17 @@ hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, int fields, 
         case 1: return launch_step_t<S, T, V, 64, 8>(a, grid, s, fields);
         case 2: return launch_step_t<S, T, V, 32, 8>(a, grid, s, fields);
         case 3: return launch_step_t<S, T, V, 16, 16>(a, grid, s, fields);
+        case 4: return launch_step_t<S, T, V, 64, 16>(a, grid, s, fields);
+        case 5: return launch_step_t<S, T, V, 128, 8>(a, grid, s, fields);
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
 extern const int kD2Q9Shapes[][2];
-const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}};
+const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}};
 extern const int kNumD2Q9Shapes;
-const int kNumD2Q9Shapes = 4;
+const int kNumD2Q9Shapes = 6;
 
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
                             int fields) {
