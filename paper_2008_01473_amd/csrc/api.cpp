@@ -113,6 +113,10 @@ struct lbm_ctx {
     }
 };
 
+// Width (in tiles) of the D2Q9 tile bands: about 512 nodes, so that the tiles
+// resident on one XCD cover a block a few bands tall rather than whole rows.
+static int band_width(int ntx, int bx) { return std::max(1, std::min(ntx, 512 / bx)); }
+
 int lbm_ctx::zchunk_for(int s) const {
     if (lattice == LBM_D2Q9) return 1;
     if (zchunk_override > 0) return zchunk_override;
@@ -144,18 +148,33 @@ std::vector<Tile> lbm_ctx::plan(int s, std::vector<LatticeRec>& rr) const {
         R.slow_z = R.nz < 8;
         R.tile_begin = (int)out.size();
         const int ntx = (R.nx + bx - 1) / bx, nty = (R.ny + by - 1) / by;
-        const int nzc = (lattice == LBM_D2Q9) ? 1 : (R.nz + zc - 1) / zc;
-        for (int kz = 0; kz < nzc; ++kz)
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < ntx; ++tx) {
-                    Tile t{};
-                    t.lat = (int)L;
-                    t.x0 = tx * bx;
-                    t.y0 = ty * by;
-                    t.z0 = (lattice == LBM_D2Q9) ? 0 : kz * zc;
-                    t.zn = (lattice == LBM_D2Q9) ? 1 : std::min(zc, R.nz - kz * zc);
-                    out.push_back(t);
-                }
+        if (lattice == LBM_D2Q9) {
+            const int band = band_width(ntx, bx);
+            for (int k = 0; k < ntx * nty; ++k) {
+                int tx, ty;
+                band_order(k, ntx, nty, band, tx, ty);
+                Tile t{};
+                t.lat = (int)L;
+                t.x0 = tx * bx;
+                t.y0 = ty * by;
+                t.z0 = 0;
+                t.zn = 1;
+                out.push_back(t);
+            }
+        } else {
+            const int nzc = (R.nz + zc - 1) / zc;
+            for (int kz = 0; kz < nzc; ++kz)
+                for (int ty = 0; ty < nty; ++ty)
+                    for (int tx = 0; tx < ntx; ++tx) {
+                        Tile t{};
+                        t.lat = (int)L;
+                        t.x0 = tx * bx;
+                        t.y0 = ty * by;
+                        t.z0 = kz * zc;
+                        t.zn = std::min(zc, R.nz - kz * zc);
+                        out.push_back(t);
+                    }
+        }
         R.tile_end = (int)out.size();
     }
     return out;
@@ -245,6 +264,19 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
     b.tiles_per_xcd = per;
     const int grid = 8 * per;
     if (grid == 0) return hipSuccess;
+    if (h->lattice == LBM_D2Q9 && h->params.size() == 1) {
+        int bx, by;
+        h->shape_dims(h->shape, bx, by);
+        const lbm_params& p = h->params[0];
+        b.single = 1;
+        b.ntx = (p.nx + bx - 1) / bx;
+        b.nty = (p.ny + by - 1) / by;
+        b.band = band_width(b.ntx, bx);
+        b.nx0 = p.nx;
+        b.ny0 = p.ny;
+        b.slow_x0 = p.nx < bx + 8;
+        b.slow_y0 = p.ny < by + 8;
+    }
     if (h->lattice == LBM_D2Q9) return d2q9_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
     return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
 }

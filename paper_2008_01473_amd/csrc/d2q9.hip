@@ -151,26 +151,43 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 
     const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
     if (t_idx >= args.ntiles) return;
-    const Tile tile = args.tiles[t_idx];
-    const LatticeRec& R = args.recs[tile.lat];
-    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
-    // this one starts, so one thread reads it and the whole block follows.
-    __shared__ unsigned s_skip;
-    if (threadIdx.x == 0) s_skip = __atomic_load_n(args.status + tile.lat, __ATOMIC_RELAXED);
-    __syncthreads();
-    if (s_skip != 0u) return;
-
-    const int nx = R.nx, ny = R.ny, N = nx * ny;
-    const int sx = R.slow_x, sy = R.slow_y;
-    const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + R.state_offset * 9;
-    S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + R.state_offset * 9;
+    // With one lattice the tile and the addressing come from the arguments, so
+    // the population loads do not wait for the tile and lattice records.
+    int lat, x0, y0, nx, ny, sx, sy;
+    long long soff;
+    if (args.single) {
+        int tx, ty;
+        band_order(t_idx, args.ntx, args.nty, args.band, tx, ty);
+        lat = 0;
+        x0 = tx * BX;
+        y0 = ty * BY;
+        nx = args.nx0;
+        ny = args.ny0;
+        sx = args.slow_x0;
+        sy = args.slow_y0;
+        soff = 0;
+    } else {
+        const Tile tile = args.tiles[t_idx];
+        lat = tile.lat;
+        x0 = tile.x0;
+        y0 = tile.y0;
+        const LatticeRec& Rl = args.recs[lat];
+        nx = Rl.nx;
+        ny = Rl.ny;
+        sx = Rl.slow_x;
+        sy = Rl.slow_y;
+        soff = Rl.state_offset;
+    }
+    const LatticeRec& R = args.recs[lat];
+    const int N = nx * ny;
+    const S* __restrict__ src = reinterpret_cast<const S*>(args.src) + soff * 9;
+    S* __restrict__ dst = reinterpret_cast<S*>(args.dst) + soff * 9;
     const S* pp[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
     const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref;
-    const int x0 = tile.x0, y0 = tile.y0;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
 
@@ -210,6 +227,10 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
         pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
     }
+    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
+    // this one runs, so one thread reads it and the whole block follows.
+    __shared__ unsigned s_skip;
+    if (tid == 0) s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
     s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
     s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
     s_b[(ly0 + 1) * W1 + lx0 + 1] = jy9(fown);
@@ -226,6 +247,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         }
     }
     __syncthreads();
+    if (s_skip != 0u) return;
 
     // ---- stage B: chemical potential (and pressure tensor) on tile + 2 ----
     for (int k = tid; k < H2 * W2; k += NT) {
@@ -325,12 +347,12 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         acc.status = blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
     }
     if constexpr (MODE == kStep) {
-        if (acc.status) atomicOr(args.status + tile.lat, acc.status);
+        if (acc.status) atomicOr(args.status + lat, acc.status);
     } else {
         block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
         if (threadIdx.x == 0) {
             const unsigned st = args.partial[t_idx].status;
-            if (st) atomicOr(args.status + tile.lat, st);
+            if (st) atomicOr(args.status + lat, st);
         }
     }
 }

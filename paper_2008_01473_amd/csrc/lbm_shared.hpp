@@ -3,6 +3,8 @@
 
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+
 namespace lbm {
 
 constexpr int kMaxQ = 19;
@@ -39,6 +41,21 @@ struct Tile {
     int lat, x0, y0, z0, zn, pad0, pad1, pad2;
 };
 
+// Order of the D2Q9 tiles of one lattice: bands of `band` tile columns, taken
+// left to right, each band row-major.  Work groups are dealt to the XCDs in
+// contiguous runs of this order, so the tiles resident on one XCD at a time
+// form a compact block whose halo rows are still in that XCD's L2 when the next
+// rows of the band read them.
+__host__ __device__ inline void band_order(int t, int ntx, int nty, int band, int& tx, int& ty) {
+    const int per_band = band * nty;
+    const int b = t / per_band;
+    const int r = t - b * per_band;
+    const int left = ntx - b * band;
+    const int wb = left < band ? left : band;
+    ty = r / wb;
+    tx = b * band + (r - ty * wb);
+}
+
 // Per-tile partial diagnostics, reduced per lattice in a fixed order.
 struct DiagPartial {
     double mass, momx, momy, momz, umax2, mumin, mumax;
@@ -64,6 +81,11 @@ struct StepArgs {
     double* u_out;
     double* mu_out;
     long long field_total;    // total nodes of all lattices (vector-field stride)
+    // One lattice only (single != 0): the kernels derive their tile from the
+    // block index with band_order and take the extents below from the
+    // arguments instead of loading the tile and lattice records first.
+    int single, ntx, nty, band;
+    int nx0, ny0, slow_x0, slow_y0;
 };
 
 }  // namespace lbm
