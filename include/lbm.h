@@ -223,8 +223,13 @@ int lbm_maxwell(int eos, double a, double b, double R, double T_over_Tc,
 /* Critical temperature of the chosen EOS (host, float64). */
 double lbm_critical_temperature(int eos, double a, double b, double R);
 
-/* Kernel tuning: tile shape index (see lbm_tile_shapes) and whether lbm_step
- * replays HIP graphs (1, default) or launches one kernel per step (0). */
+/* Kernel tuning: tile shape index and whether lbm_step replays HIP graphs
+ * (1, default) or launches one kernel per step (0).  An index in
+ * [0, lbm_num_tile_shapes) names the output tile of one work group, bx x by
+ * nodes; for D3Q19 it also fixes the z-chunk bz each work group sweeps (the same
+ * xy tile appears with several chunk lengths).  lbm_describe_tile_shape reports
+ * (bx, by, bz); bz is 1 for D2Q9.  Some D3Q19 float64 shapes return
+ * LBM_ERR_UNSUPPORTED (LDS).  Re-tiling synchronises the handle's stream. */
 int lbm_set_tile_shape(lbm_ctx* h, int shape_index);
 int lbm_get_tile_shape(const lbm_ctx* h);
 int lbm_num_tile_shapes(const lbm_ctx* h);

@@ -67,6 +67,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kGraphChunk = 256;   // even, so replaying a chunk keeps the buffer parity
 
+// Work-group counts the D3Q19 z-chunking may aim at (256 CUs): fewer, longer
+// chunks re-read fewer warm-up slices; more chunks fill the CUs better.
+constexpr int kNumZTargets = 3;
+constexpr long long kZTargets[kNumZTargets] = {512, 1024, 256};
+
 }  // namespace
 
 struct lbm_ctx {
@@ -77,7 +82,6 @@ struct lbm_ctx {
     std::vector<LatticeRec> recs;
     std::vector<Tile> tiles;
     int shape = 0;
-    int zchunk_override = 0;
     long long field_total = 0, state_nodes = 0;
     size_t state_bytes = 0, ws_bytes = 0;
     size_t off_recs = 0, off_tiles = 0, off_partial = 0, off_status = 0, off_diag = 0;
@@ -90,14 +94,17 @@ struct lbm_ctx {
     bool use_graphs = true;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
 
-    int num_shapes() const { return lattice == LBM_D2Q9 ? kNumD2Q9Shapes : kNumD3Q19Shapes; }
+    // A tuning index names a kernel tile shape and, for D3Q19, also how many
+    // work groups the z-chunking aims at (kZTargets): index = shape * 3 + target.
+    int num_shapes() const { return lattice == LBM_D2Q9 ? kNumD2Q9Shapes : kNumD3Q19Shapes * kNumZTargets; }
+    int kernel_shape(int s) const { return lattice == LBM_D2Q9 ? s : s / kNumZTargets; }
     void shape_dims(int s, int& bx, int& by) const {
         if (lattice == LBM_D2Q9) {
             bx = kD2Q9Shapes[s][0];
             by = kD2Q9Shapes[s][1];
         } else {
-            bx = kD3Q19Shapes[s][0];
-            by = kD3Q19Shapes[s][1];
+            bx = kD3Q19Shapes[kernel_shape(s)][0];
+            by = kD3Q19Shapes[kernel_shape(s)][1];
         }
     }
     LatticeRec* d_recs() const { return reinterpret_cast<LatticeRec*>(ws + off_recs); }
@@ -119,7 +126,6 @@ static int band_width(int ntx, int bx) { return std::max(1, std::min(ntx, 512 / 
 
 int lbm_ctx::zchunk_for(int s) const {
     if (lattice == LBM_D2Q9) return 1;
-    if (zchunk_override > 0) return zchunk_override;
     int bx, by;
     shape_dims(s, bx, by);
     long long cols = 0;
@@ -128,8 +134,8 @@ int lbm_ctx::zchunk_for(int s) const {
         cols += (long long)((p.nx + bx - 1) / bx) * ((p.ny + by - 1) / by);
         nzmax = std::max(nzmax, p.nz);
     }
-    // aim for about 4 work groups per compute unit (256 CUs), chunks of >= 16 slices
-    const long long want = 1024;
+    // aim for the index's work-group count, chunks of >= 16 slices
+    const long long want = kZTargets[s % kNumZTargets];
     int chunks = (int)std::max<long long>(1, (want + cols - 1) / cols);
     int zc = (nzmax + chunks - 1) / chunks;
     zc = std::max(zc, std::min(16, nzmax));
@@ -278,7 +284,7 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
         b.slow_y0 = p.ny < by + 8;
     }
     if (h->lattice == LBM_D2Q9) return d2q9_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
-    return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->shape, mode);
+    return d3q19_launch_step(b, grid, s, h->precision, h->variant, h->kernel_shape(h->shape), mode);
 }
 
 StepArgs base_args(lbm_ctx* h) {
@@ -397,7 +403,6 @@ int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx**
         std::vector<LatticeRec> rr = h->recs;
         h->max_tiles = std::max<int>(h->max_tiles, (int)h->plan(s, rr).size());
     }
-    h->max_tiles = std::max(h->max_tiles, 4 * h->max_tiles);   // room for smaller z-chunks
     h->shape = 0;
     h->tiles = h->plan(h->shape, h->recs);
     size_t o = 0;

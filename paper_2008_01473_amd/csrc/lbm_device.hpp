@@ -23,13 +23,16 @@ __device__ __forceinline__ float dev_logf(float x) { return __logf(x); }
 
 // Load / store at a wave-uniform base plus a 32-bit byte offset, the form the
 // hardware takes with the base in scalar registers (no 64-bit lane addresses).
+// The populations written by a step are not read again within it, so they are
+// stored non-temporally: they stream out during the kernel instead of sitting
+// dirty in L2 until the end-of-kernel write-back.
 template <typename S>
 __device__ __forceinline__ S ld_off(const S* base, unsigned idx) {
     return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(S));
 }
 template <typename S>
 __device__ __forceinline__ void st_off(S* base, unsigned idx, S v) {
-    *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(S)) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(S)));
 }
 
 // Periodic wrap of a coordinate that is at most a few nodes outside [0, n).

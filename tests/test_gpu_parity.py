@@ -97,9 +97,28 @@ def test_d3q19_fp64_droplet(scheme, form):
     sim.close()
 
 
+def test_d3q19_fp64_several_z_chunks():
+    """nz = 40 is swept as z-chunks of 16, 16 and 8 slices (each work group
+    warms its rings up on the slices below its chunk): chunk seams and the
+    ragged last chunk against the oracle."""
+    p = runtime.params("D3Q19", 20, 18, 40, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=0.9)
+    rho0 = _droplet((40, 18, 20), "vdW", 0.8, 6.0)
+    print("case D3Q19 fp64 improved 20x18x40 z-chunks", flush=True)
+    sim = runtime.LBM(p)
+    assert sim.tile_shape()[2] == 16
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [1, 6])
+    t = 0
+    for s in (1, 6):
+        sim.step(s - t)
+        t = s
+        compare(sim, p, refs[s])
+    sim.close()
+
+
 @pytest.mark.parametrize("lattice,prec", [("D2Q9", "fp64"), ("D3Q19", "fp64"), ("D2Q9", "fp32"), ("D3Q19", "fp32")])
 def test_every_tile_shape_gives_identical_populations(lattice, prec):
-    shape = (45, 70) if lattice == "D2Q9" else (16, 18, 20)
+    shape = (45, 70) if lattice == "D2Q9" else (40, 18, 20)
     nx, ny = shape[-1], shape[-2]
     nz = 1 if lattice == "D2Q9" else shape[0]
     p = runtime.params(lattice, nx, ny, nz, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec)
