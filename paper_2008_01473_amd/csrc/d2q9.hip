@@ -225,7 +225,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
         const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
+        if ((tid & ~63) + q * NT < HALO)              // waves with no halo node left skip the pulls
+            pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
     }
     // Blown-up lattices are frozen.  The flag can be raised by other blocks while
     // this one runs, so one thread reads it and the whole block follows.

@@ -284,7 +284,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             T fh[HP][19];
             pull<S, T>(pp, OX, OY, Z, f);
 #pragma unroll
-            for (int q = 0; q < HP; ++q) pull<S, T>(pp, hX[q], hY[q], Z, fh[q]);
+            for (int q = 0; q < HP; ++q)
+                if ((tid & ~63) + q * NT < HALO)          // waves with no halo node left skip the pulls
+                    pull<S, T>(pp, hX[q], hY[q], Z, fh[q]);
             s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum19(f);
             T jx, jy, jz;
             mom19(f, jx, jy, jz);
