@@ -11,6 +11,10 @@ lattice updates per second over exactly K timed steps (inputs resident in HBM).
 `roofline`: algorithmic HBM bytes of the step kernel (read and write each
 population once: 2 * Q * word bytes per node) divided by the kernel's average
 duration from HIP events recorded on the launch stream, against 8 TB/s.
+`traffic` is the HBM bytes per launch that rocprofv3 counted (FETCH_SIZE +
+WRITE_SIZE, scaled by a copy-kernel calibration) for this workload and tile
+shape, read from the `traffic-record:` lines of profiles/*.md; null when no
+record matches the current kernel sources (SHA-256 over the csrc directory).
 `cpu_baseline`: the CPU oracle on a bounded number of steps of the same lattice.
 `secondary`: the same measurement for FP32 deviation storage, the standard
 scheme, the 256^3 D3Q19 droplet and a batched coexistence sweep.
@@ -29,6 +33,43 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline: FP64 plain vs FP32/batched/adjoint, same accuracy"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2008_01473_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_sources_sha256():
+    """Hash of every source the step kernels and their tiling are built from; a
+    counter record taken on other sources no longer describes these kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_records():
+    """`traffic-record:` lines of the committed rocprofv3 summaries: HBM bytes per
+    launch from FETCH_SIZE and WRITE_SIZE, already scaled by the copy-kernel
+    calibration factors."""
+    recs = []
+    if not os.path.isdir(PROFILES):
+        return recs
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    recs.append(json.loads(line.split(":", 1)[1]))
+    return recs
+
+
+def traffic_for(name, tile, sha, recs):
+    for r in recs:
+        if r["workload"] == name and list(r["tile"]) == list(tile) and r["sources_sha256"] == sha:
+            return r["fetch_bytes"] + r["write_bytes"]
+    return None
 
 
 def parse():
@@ -241,8 +282,10 @@ def main():
         return
     graphs = not args.no_graphs
     tune = 0 if args.no_tune else 20
+    sha, recs = kernel_sources_sha256(), traffic_records()
     prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs, tune,
                    args.tile)
+    prim["roofline"]["traffic"] = traffic_for(prim["name"], prim["tile"], sha, recs)
     print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step",
           file=sys.stderr, flush=True)
     secondary = []
@@ -273,6 +316,7 @@ def main():
                 continue
             r["steps"] = k
             r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
+            r["roofline"]["traffic"] = traffic_for(r["name"], r["tile"], sha, recs)
             secondary.append(r)
             print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s)",
                   file=sys.stderr, flush=True)
@@ -294,7 +338,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": prim["workload"], "lattice": "D2Q9", "nodes": prim["nodes"],
                    "bytes_per_lup": prim["bytes_per_lup"], "tile": prim["tile"]},
-        "roofline": dict(prim["roofline"], traffic=None),
+        "roofline": prim["roofline"],
         "cpu_baseline": cpu,
         "secondary": secondary,
     }
