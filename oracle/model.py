@@ -25,7 +25,11 @@ notes of the repository):
   * lap is the isotropic stencil of operators.laplacian.
   * partial_i(phi u_i) is the i-th component of Eq. 17 applied to the field phi u_i.
   * Lambda = I / tau (BGK, "a special case" of MRT per Sec. II A); a full
-    relaxation vector may be passed for D2Q9.
+    relaxation vector may be passed for D2Q9 (Eq. 8, in the order of M's rows).
+  * with `nu` set (D2Q9), the shear rates (rows p_xx, p_xy) are 1/tau_v with
+    tau_v chosen so that the kinematic viscosity nu = eta / rho is the same at
+    every node: eta = rho c_s^2 (tau_v - 1/2) in the standard scheme (Sec. II A)
+    and eta = p_m (tau_v - 1/2) in the improved one (Sec. III).
   * the pressure-tensor divergence applies Eq. 17 to every component P_ij.
   * initial populations are the scheme's own equilibrium at (rho0, u0), with
     p_m evaluated from mu(rho0) including the -kappa lap(rho0) term.
@@ -63,6 +67,7 @@ class Params:
     scheme: str = "improved"          # "improved" | "standard"
     force_form: str = "chempot"       # "chempot" | "ptensor" (standard scheme only)
     relaxation: Optional[Sequence[float]] = None   # D2Q9 MRT rates; None => BGK 1/tau
+    nu: Optional[float] = None        # D2Q9: constant kinematic viscosity -> per-node tau_v
     extra: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -251,6 +256,14 @@ def collide(f, prm, fl=None):
         s = torch.full((9,), 1.0 / prm.tau, dtype=DT) if prm.relaxation is None \
             else torch.tensor(list(prm.relaxation), dtype=DT)
         s = s.view((9,) + (1,) * rho.ndim)
+        if prm.nu is not None:
+            s = s.expand((9,) + tuple(rho.shape)).clone()
+            if improved:
+                tau_v = prm.nu * rho / pm + 0.5          # eta = p_m (tau_v - 1/2), nu = eta / rho
+            else:
+                tau_v = torch.full_like(rho, prm.nu / CS2 + 0.5)   # eta = rho c_s^2 (tau_v - 1/2)
+            s[7] = 1.0 / tau_v
+            s[8] = 1.0 / tau_v
         m = torch.einsum("ka,a...->k...", M, f)
         meq = d2q9_equilibrium_moments(rho, u, pm, prm.scheme)
         S = torch.einsum("ka,a...->k...", M, G)
@@ -258,8 +271,8 @@ def collide(f, prm, fl=None):
             S = S + d2q9_correction_moments(correction_strengths(rho, u, pm, prm))
         mstar = m - s * (m - meq) + (1.0 - 0.5 * s) * S
         return torch.einsum("ak,k...->a...", Minv, mstar)
-    if prm.relaxation is not None:
-        raise ValueError("relaxation vectors are defined for D2Q9 only")
+    if prm.relaxation is not None or prm.nu is not None:
+        raise ValueError("relaxation vectors and nu are defined for D2Q9 only")
     feq = equilibrium(rho, u, pm, prm)
     src = G
     if improved:

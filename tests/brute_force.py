@@ -14,9 +14,27 @@ E3 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0,
       (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
 W3 = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
 
+# Lallemand-Luo moment matrix typed out as integers (rows rho, e, eps, j_x, q_x,
+# j_y, q_y, p_xx, p_xy; columns in the E2 velocity order).
+MLL = [
+    [1, 1, 1, 1, 1, 1, 1, 1, 1],
+    [-4, -1, -1, -1, -1, 2, 2, 2, 2],
+    [4, -2, -2, -2, -2, 1, 1, 1, 1],
+    [0, 1, 0, -1, 0, 1, -1, -1, 1],
+    [0, -2, 0, 2, 0, 1, -1, -1, 1],
+    [0, 0, 1, 0, -1, 1, 1, -1, -1],
+    [0, 0, -2, 0, 2, 1, 1, -1, -1],
+    [0, 1, -1, 1, -1, 0, 0, 0, 0],
+    [0, 0, 0, 0, 0, 1, -1, 1, -1],
+]
 
-def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot"):
+
+def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=None):
     """f: dict {(a, node): value}; dims = (nx, ny) or (nx, ny, nz); node = (x, y[, z]).
+    mrt (D2Q9 only): dict(s_e, s_eps, s_q, nu) -> collision in the moment basis MLL
+    with rates (1, s_e, s_eps, 1, s_q, 1, s_q, s_v, s_v); s_v = 1/tau if nu is None,
+    else 1/tau_v from nu = eta/rho with eta = rho/3 (tau_v - 1/2) (standard) or
+    p_m (tau_v - 1/2) (improved).
     Returns (f_next, fields)."""
     D = len(dims)
     E, W = (E2, W2) if D == 2 else (E3, W3)
@@ -78,6 +96,7 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot"):
         php = pm[n] - r / 3
         if scheme == "improved":
             Cii = [3.0 * x for x in dcorr[n]]
+        feqs, srcs = [], []
         for a in range(Q):
             e = E[a]
             c2 = sum(x * x for x in e)
@@ -110,6 +129,26 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot"):
                         ii = [d for d in range(3) if e[d] != 0]
                         k = [d for d in range(3) if e[d] == 0][0]
                         C = (5 * (Cii[ii[0]] + Cii[ii[1]]) - 2 * Cii[k]) / 42
-            fs = f[(a, n)] - (f[(a, n)] - feq) / tau + (1 - 0.5 / tau) * (G + C)
-            out[(a, nb(n, e))] = fs          # streaming, Eq. 10
+            feqs.append(feq)
+            srcs.append(G + C)
+        if mrt is None:
+            post = [f[(a, n)] - (f[(a, n)] - feqs[a]) / tau + (1 - 0.5 / tau) * srcs[a] for a in range(Q)]
+        else:
+            if mrt.get("nu") is None:
+                tv = tau
+            elif scheme == "improved":
+                tv = mrt["nu"] * r / pm[n] + 0.5
+            else:
+                tv = 3.0 * mrt["nu"] + 0.5
+            rates = [1.0, mrt["s_e"], mrt["s_eps"], 1.0, mrt["s_q"], 1.0, mrt["s_q"], 1.0 / tv, 1.0 / tv]
+            mstar = []
+            for k in range(9):
+                mk = sum(MLL[k][a] * f[(a, n)] for a in range(9))
+                mek = sum(MLL[k][a] * feqs[a] for a in range(9))
+                sk = sum(MLL[k][a] * srcs[a] for a in range(9))
+                mstar.append(mk - rates[k] * (mk - mek) + (1 - 0.5 * rates[k]) * sk)
+            norms = [sum(MLL[k][a] ** 2 for a in range(9)) for k in range(9)]
+            post = [sum(MLL[k][a] * mstar[k] / norms[k] for k in range(9)) for a in range(9)]
+        for a in range(Q):
+            out[(a, nb(n, E[a]))] = post[a]          # streaming, Eq. 10
     return out, {"rho": rho, "u": u, "mu": mu, "F": F}

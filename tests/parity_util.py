@@ -20,9 +20,13 @@ EOS_NAMES = {0: "vdW", 1: "CS"}
 def oracle_params(p):
     """Oracle Params equivalent to a ctypes lbm_params record."""
     E = oeos.make_eos(EOS_NAMES[p.eos], p.a, p.b, p.R)
+    relaxation, nu = None, None
+    if p.collision == 1:            # MRT: Eq. 8 rates in the order of M's rows, tau_c = 1
+        relaxation = [1.0, 1 / p.tau_e, 1 / p.tau_s, 1.0, 1 / p.tau_q, 1.0, 1 / p.tau_q, 1 / p.tau, 1 / p.tau]
+        nu = p.nu if p.nu > 0 else None
     return model.Params(lattice="D2Q9" if p.lattice == 0 else "D3Q19", eos=E, T_over_Tc=p.T_over_Tc,
                         kappa=p.kappa, tau=p.tau, scheme="improved" if p.scheme == 1 else "standard",
-                        force_form="ptensor" if p.force_form == 1 else "chempot")
+                        force_form="ptensor" if p.force_form == 1 else "chempot", relaxation=relaxation, nu=nu)
 
 
 def shape_of(p):
