@@ -16,8 +16,9 @@ WRITE_SIZE, scaled by a copy-kernel calibration) for this workload and tile
 shape, read from the `traffic-record:` lines of profiles/*.md; null when no
 record matches the current kernel sources (SHA-256 over the csrc directory).
 `cpu_baseline`: the CPU oracle on a bounded number of steps of the same lattice.
-`secondary`: the same measurement for FP32 deviation storage, the standard
-scheme, the 256^3 D3Q19 droplet and a batched coexistence sweep.
+`secondary`: the same measurement for FP32 deviation storage, the MRT collision
+at constant viscosity, the standard scheme, the 256^3 D3Q19 droplet, 4096^2
+lattices and a batched coexistence sweep, plus the adjoint's cost.
 """
 
 import argparse
@@ -150,6 +151,18 @@ def primary_spec(runtime, inputs, precision="fp64", scheme="improved", T=0.8):
     return {"name": f"d2q9_512_cs_{scheme}_{precision}", "params": [p], "rho0": rho0,
             "workload": f"D2Q9 512x512 periodic, Carnahan-Starling droplet r=80 W=5, T/Tc={T}, kappa=0.01, "
                         f"tau=0.8, {scheme} scheme, {precision}"}
+
+
+def mrt_spec(runtime, inputs, nu=0.15):
+    """The primary's droplet with the MRT collision of Eq. 8 at constant kinematic
+    viscosity nu (Fig. 1 uses 0.15 and 0.03); tau_e = tau_s = tau_q = 1."""
+    m = runtime.maxwell("CS", 0.8)
+    p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8, collision="mrt",
+                       tau_e=1.0, tau_s=1.0, tau_q=1.0, nu=nu)
+    rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
+    return {"name": "d2q9_512_cs_improved_mrt_fp64", "params": [p], "rho0": rho0,
+            "workload": f"D2Q9 512x512 periodic, Carnahan-Starling droplet r=80 W=5, T/Tc=0.8, kappa=0.01, improved "
+                        f"scheme, MRT (Eq. 8) tau_e = tau_s = tau_q = 1, constant nu = {nu}, fp64"}
 
 
 def d2q9_large_spec(runtime, inputs, precision="fp64", n=4096):
@@ -293,6 +306,7 @@ def main():
         only = set(filter(None, args.only.split(",")))
         jobs = [
             ("fp32", lambda: primary_spec(runtime, inputs, precision="fp32"), args.steps),
+            ("mrt", lambda: mrt_spec(runtime, inputs), args.steps),
             # the standard scheme blows up for this droplet at T/Tc = 0.8 (oracle too); 0.9 is stable
             ("standard", lambda: primary_spec(runtime, inputs, scheme="standard", T=0.9), args.steps),
             ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),

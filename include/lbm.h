@@ -6,7 +6,9 @@
  * D3Q19 lattices, in the paper's standard scheme (force of Eq. 13, equilibrium
  * of Eq. 11, collision of Eq. 9) and in its improved scheme (p_m = (1 + mu)/3,
  * force of Eq. 24, equilibrium of Eq. 27, correction term of Eqs. 28-29), with
- * the BGK special case Lambda = I / tau of the relaxation matrix (Eq. 8).
+ * the BGK special case Lambda = I / tau of the relaxation matrix (Eq. 8) or,
+ * on D2Q9, the full relaxation matrix of Eq. 8 (optionally with a per-node
+ * shear rate that holds the kinematic viscosity constant).
  * The chemical potential is Eq. 2 with the van der Waals free energy of Eq. 30
  * or a Carnahan-Starling free energy; gradients use the isotropic stencil of
  * Eq. 17 and the Laplacian its isotropic counterpart with the same weights.
@@ -62,6 +64,7 @@ enum lbm_eos       { LBM_EOS_VDW = 0, LBM_EOS_CS = 1 };
 enum lbm_scheme    { LBM_STANDARD = 0, LBM_IMPROVED = 1 };
 enum lbm_force     { LBM_FORCE_CHEMPOT = 0, LBM_FORCE_PTENSOR = 1 };
 enum lbm_precision { LBM_FP64 = 0, LBM_FP32_DEV = 1 };
+enum lbm_collision { LBM_BGK = 0, LBM_MRT = 1 };
 
 /* Per-lattice blow-up flags, OR-ed into lbm_diag.status. */
 enum lbm_blowup_bits {
@@ -92,7 +95,22 @@ enum lbm_blowup_bits {
  *   rho_ref, pm_ref  FP32_DEV reference state; values <= 0 select the defaults
  *                rho_ref = (rho_g + rho_l)/2 of the Maxwell construction and
  *                pm_ref = (1 + mu_sat)/3 (improved) or rho_ref/3 (standard).
- * All lattices of one batch must share lattice, scheme, force_form, precision.
+ *   collision    LBM_BGK (zero, the default): Lambda = I/tau.
+ *                LBM_MRT (D2Q9 only): the relaxation matrix of Eq. 8 in the
+ *                moment basis (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy),
+ *                Lambda = diag(1, 1/tau_e, 1/tau_s, 1, 1/tau_q, 1, 1/tau_q,
+ *                1/tau_v, 1/tau_v) (tau_c = 1 for the conserved moments), applied
+ *                as in Eq. 9 (standard) and Eq. 28 (improved).
+ *   tau_e, tau_s, tau_q  MRT relaxation times of e (bulk viscosity), eps and q
+ *                (each > 0.5); the paper leaves them free.
+ *   nu           MRT shear relaxation: nu <= 0 gives tau_v = tau; nu > 0 holds the
+ *                kinematic viscosity nu = eta/rho constant, i.e. tau_v = 3 nu + 1/2
+ *                in the standard scheme (eta = rho c_s^2 (tau_v - 1/2), Sec. II A) and
+ *                tau_v = nu rho / p_m + 1/2 per node in the improved scheme
+ *                (eta = p_m (tau_v - 1/2), Sec. III).
+ * A zero-initialised tail (collision, tau_e, tau_s, tau_q, nu all 0) is BGK.
+ * All lattices of one batch must share lattice, scheme, force_form, precision;
+ * collision and its rates may differ between lattices.
  */
 typedef struct {
     int lattice, nx, ny, nz;
@@ -101,6 +119,8 @@ typedef struct {
     double T_over_Tc, kappa, tau;
     int scheme, force_form, precision;
     double rho_ref, pm_ref;
+    int collision, reserved;
+    double tau_e, tau_s, tau_q, nu;
 } lbm_params;
 
 /*
@@ -205,7 +225,8 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc);
  *   parameter terms through mu.
  * lbm_adjoint_init: dL/drho0 of the initialisation f = f_eq(rho0, u0 = 0) from
  *   lam0 = dL/df(0); grad_rho0 [N] is overwritten, grad incremented.
- * Returns LBM_ERR_UNSUPPORTED for D3Q19, batches or the pressure-tensor force.
+ * Returns LBM_ERR_UNSUPPORTED for D3Q19, batches, the pressure-tensor force or
+ * the MRT collision (lbm_adjoint_workspace_bytes then returns 0).
  */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h);
 int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out, void* ws,

@@ -16,6 +16,7 @@ LBM_EOS_VDW, LBM_EOS_CS = 0, 1
 LBM_STANDARD, LBM_IMPROVED = 0, 1
 LBM_FORCE_CHEMPOT, LBM_FORCE_PTENSOR = 0, 1
 LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_BGK, LBM_MRT = 0, 1
 
 
 class lbm_params(ctypes.Structure):
@@ -23,7 +24,9 @@ class lbm_params(ctypes.Structure):
                 ("eos", c_int), ("a", c_double), ("b", c_double), ("R", c_double),
                 ("T_over_Tc", c_double), ("kappa", c_double), ("tau", c_double),
                 ("scheme", c_int), ("force_form", c_int), ("precision", c_int),
-                ("rho_ref", c_double), ("pm_ref", c_double)]
+                ("rho_ref", c_double), ("pm_ref", c_double),
+                ("collision", c_int), ("reserved", c_int),
+                ("tau_e", c_double), ("tau_s", c_double), ("tau_q", c_double), ("nu", c_double)]
 
 
 class lbm_diag(ctypes.Structure):

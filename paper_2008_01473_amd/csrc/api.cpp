@@ -206,6 +206,13 @@ int check_params(const lbm_params& p) {
         return fail(LBM_ERR_ARG, "the pressure-tensor force is defined for the standard scheme only");
     if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return fail(LBM_ERR_ARG, "bad precision");
     if (p.a == 0) return fail(LBM_ERR_ARG, "a must be > 0 (T_c is proportional to a)");
+    if (p.collision != LBM_BGK && p.collision != LBM_MRT) return fail(LBM_ERR_ARG, "bad collision");
+    if (p.collision == LBM_MRT) {
+        if (p.lattice != LBM_D2Q9) return fail(LBM_ERR_UNSUPPORTED, "the MRT collision is implemented for D2Q9");
+        if (!(p.tau_e > 0.5) || !(p.tau_s > 0.5) || !(p.tau_q > 0.5))
+            return fail(LBM_ERR_ARG, "MRT relaxation times tau_e, tau_s, tau_q must be > 0.5");
+        if (!(p.nu == p.nu)) return fail(LBM_ERR_ARG, "nu must be a number");
+    }
     return LBM_OK;
 }
 
@@ -224,6 +231,13 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     R.kappa = p.kappa;
     R.omega = 1.0 / p.tau;
     R.rho_max = host::rho_limit(p.eos, p.b);
+    if (p.collision == LBM_MRT) {
+        R.mrt = 1;
+        R.s_e = 1.0 / p.tau_e;
+        R.s_eps = 1.0 / p.tau_s;
+        R.s_q = 1.0 / p.tau_q;
+        R.nu = p.nu > 0 ? p.nu : 0.0;
+    }
     if (p.precision == LBM_FP64) {
         R.rho_ref = 0.0;
         R.pm_ref = 0.0;
@@ -270,6 +284,7 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
     b.tiles_per_xcd = per;
     const int grid = 8 * per;
     if (grid == 0) return hipSuccess;
+    for (const auto& R : h->recs) b.any_mrt |= R.mrt;
     if (h->lattice == LBM_D2Q9 && h->params.size() == 1) {
         int bx, by;
         h->shape_dims(h->shape, bx, by);
@@ -711,9 +726,10 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
 namespace {
 int adjoint_check(lbm_ctx* h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
-    if (h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->variant == kStdPtensor)
+    if (h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->variant == kStdPtensor || h->recs[0].mrt)
         return fail(LBM_ERR_UNSUPPORTED,
-                    "the adjoint is implemented for one D2Q9 lattice, improved or chemical-potential standard scheme");
+                    "the adjoint is implemented for one D2Q9 BGK lattice, improved or chemical-potential standard "
+                    "scheme");
     if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
     return LBM_OK;
 }
@@ -724,7 +740,7 @@ double adjoint_dRT(const lbm_ctx* h) {
 }  // namespace
 
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h) {
-    if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1) return 0;
+    if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->recs[0].mrt) return 0;
     return align256(adjoint_workspace_doubles(h->recs[0].nnodes) * sizeof(double));
 }
 

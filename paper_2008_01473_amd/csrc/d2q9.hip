@@ -106,6 +106,59 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
     pair_update<T>(f[6], f[8], uy - ux, Fy - Fx, ed2, e1d, e2d, o1d, o2d, om1);
 }
 
+// Multiple-relaxation-time collision (Eq. 9 / Eq. 28 with the relaxation matrix
+// of Eq. 8) in the moment basis (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy)
+// with rows  e: -4 + 3|e|^2,  eps: 4 - 21|e|^2/2 + 9|e|^4/2,  q_i: (-5 + 3|e|^2) e_i,
+// p_xx: e_x^2 - e_y^2,  p_xy: e_x e_y.  f holds populations minus fbar; the
+// non-equilibrium moments are formed from drho = rho - rho_ref and
+// dpm = p_m - pm_ref so that fbar's moments cancel:
+//   e - e_eq     = e(f) + 4 drho - 6 dpm - 3 rho u^2       (e_eq = -4 rho + 3 rho u^2 + 6 p_m)
+//   eps - eps_eq = eps(f) - 4 drho + 9 dpm + 3 rho u^2     (eps_eq = 4 rho - 3 rho u^2 - 9 p_m)
+//   q_i - q_i,eq = q_i(f) - (3 php - rho) u_i              (q_eq = (3 p_m - 2 rho) u, Eq. 27)
+//   p_xx - ..    = p_xx(f) - rho (u_x^2 - u_y^2),  p_xy - .. = p_xy(f) - rho u_x u_y
+// Sources: S = M G (Eq. 14) = (0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2(u_x F_x - u_y F_y),
+// u_x F_y + u_y F_x) and C of Eq. 29 = (0, 3(Cxx + Cyy), 0, 0, 0, 0, 0, Cxx - Cyy, 0).
+// With D_k = -s_k (m_k - m_k,eq) + (1 - s_k/2)(S_k + C_k) (D_rho = 0, D_j = F for any
+// tau_c), f* = f + M^-1 D, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+template <typename T>
+__device__ __forceinline__ void collide_mrt(T f[9], T rho, T drho, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
+                                            T Cyy, T s_e, T s_eps, T s_q, T s_v) {
+    const T ax = (f[1] + f[2]) + (f[3] + f[4]);
+    const T dg = (f[5] + f[6]) + (f[7] + f[8]);
+    const T m_e = T(2) * dg - ax - T(4) * f[0];
+    const T m_eps = T(4) * f[0] - T(2) * ax + dg;
+    const T m_qx = T(2) * (f[3] - f[1]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    const T m_qy = T(2) * (f[4] - f[2]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    const T m_pxx = (f[1] + f[3]) - (f[2] + f[4]);
+    const T m_pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const T ru2 = rho * (ux * ux + uy * uy);
+    const T uF = ux * Fx + uy * Fy;
+    const T g = T(3) * php - rho;
+    const T d_e = -s_e * (m_e + T(4) * drho - T(6) * dpm - T(3) * ru2) +
+                  (T(1) - T(0.5) * s_e) * (T(6) * uF + T(3) * (Cxx + Cyy));
+    const T d_eps = -s_eps * (m_eps - T(4) * drho + T(9) * dpm + T(3) * ru2) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+    const T hq = T(1) - T(0.5) * s_q;
+    const T d_qx = -s_q * (m_qx - g * ux) - hq * Fx;
+    const T d_qy = -s_q * (m_qy - g * uy) - hq * Fy;
+    const T hv = T(1) - T(0.5) * s_v;
+    const T d_pxx = -s_v * (m_pxx - rho * (ux * ux - uy * uy)) + hv * (T(2) * (ux * Fx - uy * Fy) + (Cxx - Cyy));
+    const T d_pxy = -s_v * (m_pxy - rho * ux * uy) + hv * (ux * Fy + uy * Fx);
+    f[0] += (d_eps - d_e) * T(1.0 / 9.0);
+    const T A = -(d_e + T(2) * d_eps) * T(1.0 / 36.0);
+    const T B = (T(2) * d_e + d_eps) * T(1.0 / 36.0);
+    const T Ax = Fx * T(1.0 / 6.0) - d_qx * T(1.0 / 6.0), Ay = Fy * T(1.0 / 6.0) - d_qy * T(1.0 / 6.0);
+    const T P4 = d_pxx * T(0.25), X4 = d_pxy * T(0.25);
+    f[1] += A + Ax + P4;
+    f[3] += A - Ax + P4;
+    f[2] += A + Ay - P4;
+    f[4] += A - Ay - P4;
+    const T X = Fx * T(1.0 / 6.0) + d_qx * T(1.0 / 12.0), Y = Fy * T(1.0 / 6.0) + d_qy * T(1.0 / 12.0);
+    f[5] += B + X + Y + X4;
+    f[6] += B - X + Y - X4;
+    f[7] += B - X - Y + X4;
+    f[8] += B + X - Y - X4;
+}
+
 // Equilibrium minus reference for initialisation (same closed forms, no force).
 template <typename T>
 __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy, T dpm, T php) {
@@ -134,7 +187,9 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 //   D  collision (Eq. 9 / Eq. 28 with Lambda = I/tau) and store, or field output
 // MODE (lbm::Mode) selects collide-and-store, the same plus per-tile
 // diagnostics, or writing rho, u, mu of the current time level.
-template <typename S, typename T, int V, int BX, int BY, int MODE>
+// COLL = 0: every lattice of the launch collides with BGK; COLL = 1: the lattice
+// record chooses BGK or MRT (a BGK-only launch carries no MRT code).
+template <typename S, typename T, int V, int BX, int BY, int MODE, int COLL>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
@@ -334,11 +389,21 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 dpm = drho * T(1.0 / 3.0);
                 php = T(0);
             }
-            collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+            if (COLL == 1 && R.mrt) {
+                // shear rate: 1/tau, or from the constant kinematic viscosity nu = eta / rho with
+                // eta = p_m (tau_v - 1/2) (improved, Sec. III) or rho/3 (tau_v - 1/2) (standard)
+                T s_v = omega;
+                if (R.nu > 0) {
+                    const T nu = (T)R.nu;
+                    s_v = IMP ? dev_rcp(nu * r * dev_rcp(pm_ref + dpm) + T(0.5)) : dev_rcp(T(3) * nu + T(0.5));
+                }
+                collide_mrt<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
+            } else {
+                collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+            }
 #pragma unroll
             for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fown[a]);
         }
-        (void)pm_ref;
         acc.mass = (double)drho;
         acc.mx = (double)(r * ux);
         acc.my = (double)(r * uy);
@@ -439,12 +504,17 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 namespace {
 template <typename S, typename T, int V, int BX, int BY>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
+    const dim3 g(grid), b(BX * BY);
     if (mode == kFields)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0>), g, b, 0, s, a);
+    else if (mode == kStepDiag && a.any_mrt)
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag, 1>), g, b, 0, s, a);
     else if (mode == kStepDiag)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag, 0>), g, b, 0, s, a);
+    else if (a.any_mrt)
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep, 1>), g, b, 0, s, a);
     else
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep, 0>), g, b, 0, s, a);
     return hipGetLastError();
 }
 

@@ -34,6 +34,10 @@ struct LatticeRec {
     double rho_ref, pm_ref, mu_ref;     // FP32 deviation reference (zero for FP64)
     double fbar[kMaxQ];                 // reference populations f_eq(rho_ref, 0, pm_ref)
     int tile_begin, tile_end;           // range of this lattice's tiles in the tile list
+    // D2Q9 MRT (Eq. 8): mrt != 0 selects it; rates of e, eps, q; shear rate
+    // omega (nu <= 0) or from the constant kinematic viscosity nu.
+    int mrt, pad_mrt;
+    double s_e, s_eps, s_q, nu;
 };
 
 // One unit of work: an output tile (2D) or an output column chunk (3D).
@@ -86,6 +90,7 @@ struct StepArgs {
     // arguments instead of loading the tile and lattice records first.
     int single, ntx, nty, band;
     int nx0, ny0, slow_x0, slow_y0;
+    int any_mrt;              // some lattice of the launch uses the MRT collision (D2Q9)
 };
 
 }  // namespace lbm

@@ -15,6 +15,7 @@ _EOS = {"vdW": _lib.LBM_EOS_VDW, "CS": _lib.LBM_EOS_CS}
 _SCHEME = {"standard": _lib.LBM_STANDARD, "improved": _lib.LBM_IMPROVED}
 _FORCE = {"chempot": _lib.LBM_FORCE_CHEMPOT, "ptensor": _lib.LBM_FORCE_PTENSOR}
 _PREC = {"fp64": _lib.LBM_FP64, "fp32": _lib.LBM_FP32_DEV}
+_COLLISION = {"bgk": _lib.LBM_BGK, "mrt": _lib.LBM_MRT}
 
 # default EOS constants: the paper's vdW values (Sec. IV A) and the CS reading
 # with the same critical density 3.5 and critical temperature 1/14
@@ -23,7 +24,10 @@ EOS_DEFAULTS = {"vdW": (9.0 / 392.0, 2.0 / 21.0), "CS": (0.0282217394824, 0.1490
 
 def params(lattice="D2Q9", nx=64, ny=64, nz=1, eos="vdW", a=None, b=None, R=1.0, T_over_Tc=0.8,
            kappa=0.02, tau=1.0, scheme="improved", force_form="chempot", precision="fp64",
-           rho_ref=0.0, pm_ref=0.0):
+           rho_ref=0.0, pm_ref=0.0, collision="bgk", tau_e=1.0, tau_s=1.0, tau_q=1.0, nu=0.0):
+    """An lbm_params record (see include/lbm.h).  collision="mrt" selects the
+    relaxation matrix of Eq. 8 with rates 1/tau_e, 1/tau_s, 1/tau_q and a shear
+    rate from tau (nu <= 0) or from a constant kinematic viscosity nu."""
     da, db = EOS_DEFAULTS[eos]
     p = lbm_params()
     p.lattice, p.nx, p.ny, p.nz = _LATTICE[lattice], nx, ny, nz
@@ -31,6 +35,8 @@ def params(lattice="D2Q9", nx=64, ny=64, nz=1, eos="vdW", a=None, b=None, R=1.0,
     p.T_over_Tc, p.kappa, p.tau = T_over_Tc, kappa, tau
     p.scheme, p.force_form, p.precision = _SCHEME[scheme], _FORCE[force_form], _PREC[precision]
     p.rho_ref, p.pm_ref = rho_ref, pm_ref
+    p.collision = _COLLISION[collision]
+    p.tau_e, p.tau_s, p.tau_q, p.nu = tau_e, tau_s, tau_q, nu
     return p
 
 
