@@ -26,6 +26,16 @@ notes of the repository):
   * partial_i(phi u_i) is the i-th component of Eq. 17 applied to the field phi u_i.
   * Lambda = I / tau (BGK, "a special case" of MRT per Sec. II A); a full
     relaxation vector may be passed for D2Q9 (Eq. 8, in the order of M's rows).
+  * with `walls` set (D2Q9), the lattice is bounded in y by two plates halfway
+    between rows -1 / 0 and ny-1 / ny that move along x with the given speeds
+    (Sec. IV B's channel): a population that would stream out of a plate comes back
+    at the node it left, reversed, plus feq_b - feq_-b of the scheme's own
+    equilibrium at the node's rho, p_m and the plate velocity U_w (halfway
+    bounce-back with a moving-wall term; for the standard equilibrium this is the
+    familiar 6 w_b rho (e_b . U_w); the paper cites its no-slip scheme without
+    stating it, and the improved equilibrium's odd part carries p_m).  The
+    stencils see beyond a plate the mirror image of the fluid: rho, mu and
+    phi u_x even, phi u_y odd (an impermeable, neutrally wetting plate).
   * with `nu` set (D2Q9), the shear rates (rows p_xx, p_xy) are 1/tau_v with
     tau_v chosen so that the kinematic viscosity nu = eta / rho is the same at
     every node: eta = rho c_s^2 (tau_v - 1/2) in the standard scheme (Sec. II A)
@@ -48,7 +58,7 @@ D3Q19 (not in the paper) is an extension built by the same rules:
 """
 
 from dataclasses import dataclass, field
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -68,6 +78,7 @@ class Params:
     force_form: str = "chempot"       # "chempot" | "ptensor" (standard scheme only)
     relaxation: Optional[Sequence[float]] = None   # D2Q9 MRT rates; None => BGK 1/tau
     nu: Optional[float] = None        # D2Q9: constant kinematic viscosity -> per-node tau_v
+    walls: Optional[Tuple[float, float]] = None   # D2Q9: plate speeds (bottom, top) along x
     extra: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -79,6 +90,8 @@ class Params:
             raise ValueError(self.force_form)
         if self.scheme == "improved" and self.force_form != "chempot":
             raise ValueError("the improved scheme is defined with the chemical-potential force (Eq. 24)")
+        if self.walls is not None and (self.lattice.Q != 9 or self.force_form != "chempot"):
+            raise ValueError("plates are implemented for D2Q9 with the chemical-potential force")
 
     @property
     def T(self):
@@ -94,9 +107,18 @@ def density_momentum(f, lat):
     return rho, j
 
 
+def _stencil(op, phi, prm, parity=1.0, *args):
+    """Apply a stencil; with plates, on phi extended by one mirror row beyond each
+    plate (times `parity`, -1 for a wall-normal component), cropped back."""
+    if prm.walls is None:
+        return op(phi, prm.lattice, *args)
+    ext = torch.cat([parity * phi[..., :1, :], phi, parity * phi[..., -1:, :]], dim=-2)
+    return op(ext, prm.lattice, *args)[..., 1:-1, :]
+
+
 def chemical_potential(rho, prm):
     """Eq. 2 with the bulk part of Eq. 30 (or the CS reading)."""
-    return prm.eos.mu(rho, prm.T) - prm.kappa * laplacian(rho, prm.lattice)
+    return prm.eos.mu(rho, prm.T) - prm.kappa * _stencil(laplacian, rho, prm)
 
 
 def modified_pressure(mu):
@@ -120,9 +142,9 @@ def pressure_tensor(rho, prm):
 def force(rho, mu, prm):
     lat = prm.lattice
     if prm.scheme == "improved":
-        return (1.0 / 3.0 - rho) * grad(mu, lat)                      # Eq. 24
+        return (1.0 / 3.0 - rho) * _stencil(grad, mu, prm)            # Eq. 24
     if prm.force_form == "chempot":
-        return grad(rho * CS2, lat) - rho * grad(mu, lat)             # Eq. 13, right
+        return _stencil(grad, rho * CS2, prm) - rho * _stencil(grad, mu, prm)   # Eq. 13, right
     return grad(rho * CS2, lat) - divergence_tensor(pressure_tensor(rho, prm), lat)  # Eq. 13, left
 
 
@@ -153,7 +175,8 @@ def guo_forcing(u, F, lat):
 def correction_strengths(rho, u, pm, prm):
     """d_i = partial_i(phi u_i) with phi = rho c_s^2 - p_m (Eq. 29), each partial from Eq. 17."""
     phi = rho * CS2 - pm
-    return torch.stack([partial(phi * u[i], prm.lattice, i) for i in range(prm.lattice.D)])
+    return torch.stack([_stencil(partial, phi * u[i], prm, -1.0 if i == 1 else 1.0, i)
+                        for i in range(prm.lattice.D)])
 
 
 def d2q9_correction_moments(d):
@@ -292,9 +315,33 @@ def stream(fstar, lat):
     return out
 
 
+def bounce_back(out, fstar, fl, prm):
+    """Plates (see the module notes): replace the populations that streamed in from
+    beyond a plate by the reversed ones of the same node plus the moving-wall term,
+    evaluated with the node's rho and p_m of the collision (fields `fl`)."""
+    lat = prm.lattice
+    e = lat.e.tolist()
+    for row, U in ((0, prm.walls[0]), (-1, prm.walls[1])):
+        rho, pm = fl["rho"][row:row + 1 if row == 0 else None, :], fl["pm"][row:row + 1 if row == 0 else None, :]
+        uw = torch.zeros((2,) + tuple(rho.shape), dtype=DT)
+        uw[0] = U
+        feq = equilibrium(rho, uw, pm, prm)
+        into = 1 if row == 0 else -1          # e_y of the populations coming back from this plate
+        for a in range(lat.Q):
+            if e[a][1] == into:
+                opp = e.index([-e[a][0], -e[a][1]])
+                out[a, row, :] = fstar[opp, row, :] + (feq[a] - feq[opp])[0]
+    return out
+
+
 def step(f, prm):
     """One time step: returns f at t + 1 (post-streaming, pre-collision)."""
-    return stream(collide(f, prm), prm.lattice)
+    fl = fields(f, prm)
+    fstar = collide(f, prm, fl)
+    out = stream(fstar, prm.lattice)
+    if prm.walls is not None:
+        out = bounce_back(out, fstar, fl, prm)
+    return out
 
 
 def run(f, prm, n):

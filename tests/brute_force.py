@@ -29,12 +29,18 @@ MLL = [
 ]
 
 
-def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=None):
+def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=None, walls=None):
     """f: dict {(a, node): value}; dims = (nx, ny) or (nx, ny, nz); node = (x, y[, z]).
     mrt (D2Q9 only): dict(s_e, s_eps, s_q, nu) -> collision in the moment basis MLL
     with rates (1, s_e, s_eps, 1, s_q, 1, s_q, s_v, s_v); s_v = 1/tau if nu is None,
     else 1/tau_v from nu = eta/rho with eta = rho/3 (tau_v - 1/2) (standard) or
     p_m (tau_v - 1/2) (improved).
+    walls (D2Q9 only): (U_bottom, U_top); plates halfway outside rows 0 and ny-1.
+    A stencil reaching past a plate reads the mirror node (row -1 -> 0, -2 -> 1,
+    ny -> ny-1, ...), negated for the y component of phi u; a population
+    leaving through a plate is pushed back into its own node reversed, plus the
+    difference of the node's closed-form equilibrium (its rho and p_m) at the plate
+    velocity between the reversed direction and the leaving one.
     Returns (f_next, fields)."""
     D = len(dims)
     E, W = (E2, W2) if D == 2 else (E3, W3)
@@ -45,11 +51,19 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=N
     def nb(n, e, s=1):
         return tuple((n[d] + s * e[d]) % dims[d] for d in range(D))
 
-    def grad(field, n):
-        return [3.0 * sum(W[a] * field[nb(n, E[a])] * E[a][d] for a in range(Q)) for d in range(D)]
+    def val(field, n, e, odd=False):
+        m = [n[d] + e[d] for d in range(D)]
+        sign = 1.0
+        if walls is not None and not 0 <= m[1] < dims[1]:
+            m[1] = -1 - m[1] if m[1] < 0 else 2 * dims[1] - 1 - m[1]
+            sign = -1.0 if odd else 1.0
+        return sign * field[tuple(m[d] % dims[d] for d in range(D))]
+
+    def grad(field, n, odd=False):
+        return [3.0 * sum(W[a] * val(field, n, E[a], odd) * E[a][d] for a in range(Q)) for d in range(D)]
 
     def lap(field, n):
-        return 6.0 * sum(W[a] * (field[nb(n, E[a])] - field[n]) for a in range(1, Q))
+        return 6.0 * sum(W[a] * (val(field, n, E[a]) - field[n]) for a in range(1, Q))
 
     rho = {n: sum(f[(a, n)] for a in range(Q)) for n in nodes}
     j = {n: [sum(E[a][d] * f[(a, n)] for a in range(Q)) for d in range(D)] for n in nodes}
@@ -87,7 +101,7 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=N
     if scheme == "improved":
         psi = [{n: (rho[n] / 3 - pm[n]) * u[n][d] for n in nodes} for d in range(D)]
         for n in nodes:
-            dcorr[n] = [3.0 * sum(W[a] * psi[d][nb(n, E[a])] * E[a][d] for a in range(Q)) for d in range(D)]
+            dcorr[n] = [3.0 * sum(W[a] * val(psi[d], n, E[a], d == 1) * E[a][d] for a in range(Q)) for d in range(D)]
 
     out = {}
     for n in nodes:
@@ -96,18 +110,26 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=N
         php = pm[n] - r / 3
         if scheme == "improved":
             Cii = [3.0 * x for x in dcorr[n]]
+        def feq_of(a, vel):
+            e = E[a]
+            c2 = sum(x * x for x in e)
+            eu = sum(e[d] * vel[d] for d in range(D))
+            vsq = sum(x * x for x in vel)
+            val = W[a] * r * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * vsq)
+            if scheme == "improved":
+                rest = 1.0 if a == 0 else 0.0
+                if D == 2:
+                    val += 3 * php * (W[a] - rest) + 4.5 * php * W[a] * eu * (3 * c2 - 4)
+                else:
+                    val += 3 * php * (W[a] - rest) + 9.0 * php * W[a] * eu * (3 * c2 - 5)
+            return val
+
         feqs, srcs = [], []
         for a in range(Q):
             e = E[a]
             c2 = sum(x * x for x in e)
             eu = sum(e[d] * uu[d] for d in range(D))
-            feq = W[a] * r * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * usq)
-            if scheme == "improved":
-                rest = 1.0 if a == 0 else 0.0
-                if D == 2:
-                    feq += 3 * php * (W[a] - rest) + 4.5 * php * W[a] * eu * (3 * c2 - 4)
-                else:
-                    feq += 3 * php * (W[a] - rest) + 9.0 * php * W[a] * eu * (3 * c2 - 5)
+            feq = feq_of(a, uu)
             G = W[a] * sum((3 * (e[d] - uu[d]) + 9 * eu * e[d]) * FF[d] for d in range(D))
             C = 0.0
             if scheme == "improved":
@@ -150,5 +172,11 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=N
             norms = [sum(MLL[k][a] ** 2 for a in range(9)) for k in range(9)]
             post = [sum(MLL[k][a] * mstar[k] / norms[k] for k in range(9)) for a in range(9)]
         for a in range(Q):
-            out[(a, nb(n, E[a]))] = post[a]          # streaming, Eq. 10
+            ty = n[1] + E[a][1] if D == 2 else None
+            if walls is not None and not 0 <= ty < dims[1]:
+                b = E.index(tuple(-x for x in E[a]))
+                U = walls[0] if ty < 0 else walls[1]
+                out[(b, n)] = post[a] + feq_of(b, (U, 0.0)) - feq_of(a, (U, 0.0))
+            else:
+                out[(a, nb(n, E[a]))] = post[a]          # streaming, Eq. 10
     return out, {"rho": rho, "u": u, "mu": mu, "F": F}
