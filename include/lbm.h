@@ -108,7 +108,19 @@ enum lbm_blowup_bits {
  *                in the standard scheme (eta = rho c_s^2 (tau_v - 1/2), Sec. II A) and
  *                tau_v = nu rho / p_m + 1/2 per node in the improved scheme
  *                (eta = p_m (tau_v - 1/2), Sec. III).
- * A zero-initialised tail (collision, tau_e, tau_s, tau_q, nu all 0) is BGK.
+ *   walls        0: periodic in y.  1 (D2Q9, chemical-potential force, ny >= 4):
+ *                the lattice is bounded in y by two plates, halfway between rows
+ *                -1 / 0 and ny-1 / ny, moving along x at wall_u_bottom / wall_u_top
+ *                (the channel of Sec. IV B).  A population that would stream in
+ *                from beyond a plate is the node's own reversed population plus
+ *                feq_b - feq_-b of the scheme's equilibrium (Eq. 11 or Eq. 27) at the
+ *                node's rho, p_m and the plate velocity (halfway bounce-back; the
+ *                paper cites its no-slip scheme without stating it).  The stencils
+ *                see beyond a plate the mirror image of the fluid (rho, mu, phi u_x
+ *                even; phi u_y odd).  x stays periodic.
+ *   wall_u_bottom, wall_u_top  plate velocities along x (lattice units)
+ * A zero-initialised tail (collision, tau_e, tau_s, tau_q, nu, walls all 0) is
+ * BGK on a periodic lattice.
  * All lattices of one batch must share lattice, scheme, force_form, precision;
  * collision and its rates may differ between lattices.
  */
@@ -121,6 +133,8 @@ typedef struct {
     double rho_ref, pm_ref;
     int collision, reserved;
     double tau_e, tau_s, tau_q, nu;
+    int walls, reserved2;
+    double wall_u_bottom, wall_u_top;
 } lbm_params;
 
 /*
@@ -225,8 +239,8 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc);
  *   parameter terms through mu.
  * lbm_adjoint_init: dL/drho0 of the initialisation f = f_eq(rho0, u0 = 0) from
  *   lam0 = dL/df(0); grad_rho0 [N] is overwritten, grad incremented.
- * Returns LBM_ERR_UNSUPPORTED for D3Q19, batches, the pressure-tensor force or
- * the MRT collision (lbm_adjoint_workspace_bytes then returns 0).
+ * Returns LBM_ERR_UNSUPPORTED for D3Q19, batches, the pressure-tensor force,
+ * the MRT collision or plates (lbm_adjoint_workspace_bytes then returns 0).
  */
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h);
 int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out, void* ws,

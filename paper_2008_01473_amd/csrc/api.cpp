@@ -213,6 +213,15 @@ int check_params(const lbm_params& p) {
             return fail(LBM_ERR_ARG, "MRT relaxation times tau_e, tau_s, tau_q must be > 0.5");
         if (!(p.nu == p.nu)) return fail(LBM_ERR_ARG, "nu must be a number");
     }
+    if (p.walls != 0) {
+        if (p.walls != 1) return fail(LBM_ERR_ARG, "walls must be 0 or 1");
+        if (p.lattice != LBM_D2Q9) return fail(LBM_ERR_UNSUPPORTED, "plates are implemented for D2Q9");
+        if (p.force_form != LBM_FORCE_CHEMPOT)
+            return fail(LBM_ERR_UNSUPPORTED, "plates are implemented with the chemical-potential force");
+        if (p.ny < 4) return fail(LBM_ERR_ARG, "a lattice with plates needs ny >= 4");
+        if (!std::isfinite(p.wall_u_bottom) || !std::isfinite(p.wall_u_top))
+            return fail(LBM_ERR_ARG, "plate velocities must be finite");
+    }
     return LBM_OK;
 }
 
@@ -231,6 +240,11 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     R.kappa = p.kappa;
     R.omega = 1.0 / p.tau;
     R.rho_max = host::rho_limit(p.eos, p.b);
+    if (p.walls) {
+        R.walls = 1;
+        R.wall_u0 = p.wall_u_bottom;
+        R.wall_u1 = p.wall_u_top;
+    }
     if (p.collision == LBM_MRT) {
         R.mrt = 1;
         R.s_e = 1.0 / p.tau_e;
@@ -284,7 +298,10 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
     b.tiles_per_xcd = per;
     const int grid = 8 * per;
     if (grid == 0) return hipSuccess;
-    for (const auto& R : h->recs) b.any_mrt |= R.mrt;
+    for (const auto& R : h->recs) {
+        b.any_mrt |= R.mrt;
+        b.any_plates |= R.walls;
+    }
     if (h->lattice == LBM_D2Q9 && h->params.size() == 1) {
         int bx, by;
         h->shape_dims(h->shape, bx, by);
@@ -726,7 +743,8 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
 namespace {
 int adjoint_check(lbm_ctx* h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
-    if (h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->variant == kStdPtensor || h->recs[0].mrt)
+    if (h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->variant == kStdPtensor || h->recs[0].mrt ||
+        h->recs[0].walls)
         return fail(LBM_ERR_UNSUPPORTED,
                     "the adjoint is implemented for one D2Q9 BGK lattice, improved or chemical-potential standard "
                     "scheme");
@@ -740,7 +758,7 @@ double adjoint_dRT(const lbm_ctx* h) {
 }  // namespace
 
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h) {
-    if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->recs[0].mrt) return 0;
+    if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->recs[0].mrt || h->recs[0].walls) return 0;
     return align256(adjoint_workspace_doubles(h->recs[0].nnodes) * sizeof(double));
 }
 

@@ -37,6 +37,36 @@ __device__ __forceinline__ void pull(const S* const (&p)[9], int nx, int xm, int
     f[8] = (T)ld_off(p[8], rp + xm);
 }
 
+// Plates (lattices bounded in y, halfway between rows -1 / 0 and ny-1 / ny): the
+// node whose fields stand at row y is its mirror image beyond a plate (clamped:
+// rows further out than the stencils reach are never used).
+__device__ __forceinline__ int plate_row(int y, int ny, bool& mirrored) {
+    mirrored = y < 0 || y >= ny;
+    y = y < 0 ? -1 - y : (y >= ny ? 2 * ny - 1 - y : y);
+    return min(max(y, 0), ny - 1);
+}
+
+// Pull of a fluid node in row yc of a lattice with plates: populations that would
+// come from beyond a plate are read from the node's own slot of the reversed
+// direction, which the previous step stored already reflected (bounce-back).
+// Loads for rows past a plate are clamped in bounds and then replaced.
+template <typename S, typename T>
+__device__ __forceinline__ void pull_plates(const S* const (&p)[9], int nx, int ny, int xm, int xc, int xp,
+                                            int yc, T f[9]) {
+    const int ym = yc > 0 ? yc - 1 : yc, yp = yc < ny - 1 ? yc + 1 : yc;
+    pull<S, T>(p, nx, xm, xc, xp, ym, yc, yp, f);
+    const unsigned own = (unsigned)(yc * nx + xc);
+    if (yc == 0) {                     // N, NE, NW come back from the bottom plate
+        f[2] = (T)ld_off(p[4], own);
+        f[5] = (T)ld_off(p[7], own);
+        f[6] = (T)ld_off(p[8], own);
+    } else if (yc == ny - 1) {         // S, SW, SE come back from the top plate
+        f[4] = (T)ld_off(p[2], own);
+        f[7] = (T)ld_off(p[5], own);
+        f[8] = (T)ld_off(p[6], own);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T sum9(const T f[9]) {
     return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -187,11 +217,13 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 //   D  collision (Eq. 9 / Eq. 28 with Lambda = I/tau) and store, or field output
 // MODE (lbm::Mode) selects collide-and-store, the same plus per-tile
 // diagnostics, or writing rho, u, mu of the current time level.
-// COLL = 0: every lattice of the launch collides with BGK; COLL = 1: the lattice
-// record chooses BGK or MRT (a BGK-only launch carries no MRT code).
-template <typename S, typename T, int V, int BX, int BY, int MODE, int COLL>
+// FEAT bit 1: lattices of the launch may use the MRT collision; bit 2: they may
+// have plates (the lattice record decides); launches without them carry no such code.
+template <typename S, typename T, int V, int BX, int BY, int MODE, int FEAT>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
+    constexpr bool MRT = (FEAT & 1) != 0;
+    constexpr bool PLATES = (FEAT & 2) != 0;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     constexpr bool IMP = (V == kImproved);
     constexpr bool PT = (V == kStdPtensor);
@@ -254,11 +286,18 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     T fown[9];
     T fh[HP][9];
     int hpos[HP];
+    const bool plates = PLATES && R.walls;
+    bool own_mirror = false;
+    bool h_mirror[HP];
     {
         const int gx = x0 + lx0, gy = y0 + ly0;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
-        const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown);
+        if (plates) {
+            pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, own_mirror), fown);
+        } else {
+            const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+            pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown);
+        }
     }
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
@@ -279,17 +318,24 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         hpos[q] = ly * W3 + lx;
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
-        const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
-        if ((tid & ~63) + q * NT < HALO)              // waves with no halo node left skip the pulls
-            pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
+        h_mirror[q] = false;
+        if ((tid & ~63) + q * NT < HALO) {            // waves with no halo node left skip the pulls
+            if (plates) {
+                pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, h_mirror[q]), fh[q]);
+            } else {
+                const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+                pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
+            }
+        }
     }
     // Blown-up lattices are frozen.  The flag can be raised by other blocks while
     // this one runs, so one thread reads it and the whole block follows.
     __shared__ unsigned s_skip;
     if (tid == 0) s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
+    // a mirror image beyond a plate carries the reflected momentum (j_y negated)
     s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
     s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
-    s_b[(ly0 + 1) * W1 + lx0 + 1] = jy9(fown);
+    s_b[(ly0 + 1) * W1 + lx0 + 1] = own_mirror ? -jy9(fown) : jy9(fown);
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
         if (tid + q * NT < HALO) {
@@ -298,7 +344,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             s_rho[pos] = rho_ref + sum9(fh[q]);
             if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
                 s_a[(ly - 2) * W1 + lx - 2] = jx9(fh[q]);
-                s_b[(ly - 2) * W1 + lx - 2] = jy9(fh[q]);
+                s_b[(ly - 2) * W1 + lx - 2] = h_mirror[q] ? -jy9(fh[q]) : jy9(fh[q]);
             }
         }
     }
@@ -389,7 +435,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 dpm = drho * T(1.0 / 3.0);
                 php = T(0);
             }
-            if (COLL == 1 && R.mrt) {
+            if (MRT && R.mrt) {
                 // shear rate: 1/tau, or from the constant kinematic viscosity nu = eta / rho with
                 // eta = p_m (tau_v - 1/2) (improved, Sec. III) or rho/3 (tau_v - 1/2) (standard)
                 T s_v = omega;
@@ -400,6 +446,23 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 collide_mrt<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
             } else {
                 collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+            }
+            if (plates && (gy == 0 || gy == ny - 1)) {
+                // Populations heading into a plate are stored reflected for the next pull:
+                // f*_a + feq_-a - feq_a at the plate velocity U (along x).  The odd part of
+                // both equilibria on the diagonals is (p_m / 2)(e . U) per pair (Eq. 11:
+                // 6 w rho = rho / 6 = p_m / 2; Eq. 27 adds php / 2), and zero on N, S.
+                const T pm = IMP ? pm_ref + dpm : r * T(1.0 / 3.0);
+                if (gy == 0) {
+                    const T w = T(0.5) * pm * (T)R.wall_u0;
+                    fown[7] += w;              // SW returns as NE
+                    fown[8] -= w;              // SE returns as NW
+                }
+                if (gy == ny - 1) {
+                    const T w = T(0.5) * pm * (T)R.wall_u1;
+                    fown[5] -= w;              // NE returns as SW
+                    fown[6] += w;              // NW returns as SE
+                }
             }
 #pragma unroll
             for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fown[a]);
@@ -423,8 +486,23 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     }
 }
 
+// Where the pull of population a at node (x, y) reads: slot a of node x - e_a
+// (periodic), or, for a population coming back from a plate, the node's own slot
+// of the reversed direction.  Index within the lattice's state block.
+__device__ __forceinline__ long long slot_of(int a, int x, int y, const LatticeRec& R) {
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const int nx = R.nx, ny = R.ny;
+    const long long N = (long long)nx * ny;
+    const int sy = y - ey[a];
+    if (R.walls && (sy < 0 || sy >= ny)) return opp[a] * N + (long long)y * nx + x;
+    const int sx = ((x - ex[a]) % nx + nx) % nx, syw = (sy % ny + ny) % ny;
+    return a * N + (long long)syw * nx + sx;
+}
+
 // Initialisation: f(x, 0) = f_eq(rho0, u0) (minus fbar), written where a pull
-// finds it: state[a][x - e_a].  One thread per node of all lattices.
+// finds it (slot_of).  One thread per node of all lattices.
 template <typename S, typename T, int V>
 __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const double* rho0, const double* u0,
                             long long field_total) {
@@ -438,7 +516,9 @@ __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const do
     const int x = (int)(local % nx), y = (int)(local / nx);
     const double* r0 = rho0 + R.field_offset;
     auto at = [&](int dx, int dy) {
-        const int xx = ((x + dx) % nx + nx) % nx, yy = ((y + dy) % ny + ny) % ny;
+        const int xx = ((x + dx) % nx + nx) % nx;
+        bool m;
+        const int yy = R.walls ? plate_row(y + dy, ny, m) : ((y + dy) % ny + ny) % ny;
         return (T)r0[yy * nx + xx];
     };
     const T r = at(0, 0);
@@ -463,13 +543,8 @@ __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const do
     T feq[9];
     equilibrium<T>(feq, r, r - (T)R.rho_ref, ux, uy, dpm, php);
     S* st = state + R.state_offset * 9;
-    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const int sx = ((x - ex[a]) % nx + nx) % nx, sy = ((y - ey[a]) % ny + ny) % ny;
-        st[a * N + sy * nx + sx] = (S)feq[a];
-    }
+    for (int a = 0; a < 9; ++a) st[slot_of(a, x, y, R)] = (S)feq[a];
 }
 
 // Post-streaming populations f_a(x, t) as float64 (fbar added back), or the reverse.
@@ -483,16 +558,14 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
     if (local < 0 || local >= R.nnodes) return;
     const int nx = R.nx, ny = R.ny, N = nx * ny;
     const int x = (int)(local % nx), y = (int)(local / nx);
-    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     S* st = state + R.state_offset * 9;
     for (int a = 0; a < 9; ++a) {
-        const int sx = ((x - ex[a]) % nx + nx) % nx, sy = ((y - ey[a]) % ny + ny) % ny;
         const long long fo = (long long)a * field_total + R.field_offset + local;
+        const long long so = slot_of(a, x, y, R);
         if (GET)
-            f[fo] = (double)st[a * N + sy * nx + sx] + R.fbar[a];
+            f[fo] = (double)st[so] + R.fbar[a];
         else
-            st[a * N + sy * nx + sx] = (S)(f[fo] - R.fbar[a]);
+            st[so] = (S)(f[fo] - R.fbar[a]);
     }
 }
 
@@ -502,19 +575,39 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 // Host-side launchers (called by the runtime).
 
 namespace {
+template <typename S, typename T, int V, int BX, int BY, int MODE>
+void launch_feat(const StepArgs& a, int feat, dim3 g, dim3 b, hipStream_t s) {
+    switch (feat) {
+        case 1: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 1>), g, b, 0, s, a); return;
+        case 2:
+            if constexpr (V != kStdPtensor)      // plates are not offered with the pressure-tensor force
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 2>), g, b, 0, s, a);
+            return;
+        case 3:
+            if constexpr (V != kStdPtensor)
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 3>), g, b, 0, s, a);
+            return;
+        default: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 0>), g, b, 0, s, a); return;
+    }
+}
+
 template <typename S, typename T, int V, int BX, int BY>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
     const dim3 g(grid), b(BX * BY);
-    if (mode == kFields)
+    const int feat = (a.any_mrt ? 1 : 0) | (a.any_plates ? 2 : 0);
+    if (mode == kFields) {
+        if constexpr (V != kStdPtensor) {
+            if (a.any_plates) {
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 2>), g, b, 0, s, a);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0>), g, b, 0, s, a);
-    else if (mode == kStepDiag && a.any_mrt)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag, 1>), g, b, 0, s, a);
-    else if (mode == kStepDiag)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStepDiag, 0>), g, b, 0, s, a);
-    else if (a.any_mrt)
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep, 1>), g, b, 0, s, a);
-    else
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kStep, 0>), g, b, 0, s, a);
+    } else if (mode == kStepDiag) {
+        launch_feat<S, T, V, BX, BY, kStepDiag>(a, feat, g, b, s);
+    } else {
+        launch_feat<S, T, V, BX, BY, kStep>(a, feat, g, b, s);
+    }
     return hipGetLastError();
 }
 

@@ -38,6 +38,9 @@ struct LatticeRec {
     // omega (nu <= 0) or from the constant kinematic viscosity nu.
     int mrt, pad_mrt;
     double s_e, s_eps, s_q, nu;
+    // D2Q9 plates bounding y (walls != 0): x-velocities of the bottom and top plate.
+    int walls, pad_walls;
+    double wall_u0, wall_u1;
 };
 
 // One unit of work: an output tile (2D) or an output column chunk (3D).
@@ -91,6 +94,7 @@ struct StepArgs {
     int single, ntx, nty, band;
     int nx0, ny0, slow_x0, slow_y0;
     int any_mrt;              // some lattice of the launch uses the MRT collision (D2Q9)
+    int any_plates;           // some lattice of the launch has plates (D2Q9)
 };
 
 }  // namespace lbm

@@ -26,7 +26,8 @@ def oracle_params(p):
         nu = p.nu if p.nu > 0 else None
     return model.Params(lattice="D2Q9" if p.lattice == 0 else "D3Q19", eos=E, T_over_Tc=p.T_over_Tc,
                         kappa=p.kappa, tau=p.tau, scheme="improved" if p.scheme == 1 else "standard",
-                        force_form="ptensor" if p.force_form == 1 else "chempot", relaxation=relaxation, nu=nu)
+                        force_form="ptensor" if p.force_form == 1 else "chempot", relaxation=relaxation, nu=nu,
+                        walls=(p.wall_u_bottom, p.wall_u_top) if p.walls else None)
 
 
 def shape_of(p):

@@ -1,0 +1,148 @@
+"""GPU plates (D2Q9 lattices bounded in y by moving plates, the channel of
+Sec. IV B) against the oracle through the C ABI: float64 at 1e-12 per field for
+both schemes with BGK and MRT, float32 deviation storage, every tile shape, a
+batch mixing plates and periodic lattices, population round trips, and the
+unsupported combinations."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import eos as oeos
+from paper_2008_01473_amd import inputs
+from parity_util import compare, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2008_01473_amd import runtime  # noqa: E402  (raises if liblbm.so is missing)
+
+PLATES = (0.03, -0.05)
+
+
+def _droplet(shape, eos, t, r, noise=1e-4, seed=0, center=None):
+    m = oeos.maxwell(oeos.make_eos(eos), t)
+    return inputs.droplet(shape, m["rho_g"], m["rho_l"], r, 5.0, noise=noise, seed=seed)
+
+
+@pytest.mark.parametrize("scheme", ["improved", "standard"])
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_plates_fp64_ragged_droplet(scheme, collision):
+    extra = dict(collision="mrt", tau_e=1.1, tau_s=1.3, tau_q=0.9, nu=0.1) if collision == "mrt" else {}
+    p = runtime.params("D2Q9", 70, 45, 1, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=0.8, scheme=scheme,
+                       walls=PLATES, **extra)
+    rho0 = _droplet((45, 70), "vdW", 0.8, 12.0)
+    print(f"case D2Q9 plates fp64 {scheme}/{collision} 70x45", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [0, 1, 10, 100])
+    compare(sim, p, refs[0])
+    t = 0
+    for s in (1, 10, 100):
+        sim.step(s - t)
+        t = s
+        compare(sim, p, refs[s])
+    sim.close()
+
+
+def test_plates_droplet_touching_the_bottom_plate():
+    """A droplet cut by the bottom plate: interface and correction terms reach
+    through the mirror images; CS EOS, improved scheme, initial shear flow."""
+    shape = (36, 50)
+    p = runtime.params("D2Q9", 50, 36, 1, eos="CS", T_over_Tc=0.8, kappa=0.02, tau=0.8, walls=(0.0, 0.08))
+    m = oeos.maxwell(oeos.make_eos("CS"), 0.8)
+    y, x = np.mgrid[0:36, 0:50].astype(np.float64)
+    r = np.sqrt((x - 25.0) ** 2 + (y - 2.0) ** 2)
+    rho0 = m["rho_g"] + 0.5 * (m["rho_l"] - m["rho_g"]) * (1 - np.tanh(2 * (r - 10.0) / 5.0))
+    u0 = np.zeros((2,) + shape)
+    u0[0] = 0.08 * (y + 0.5) / 36
+    print("case D2Q9 plates fp64 CS droplet on the bottom plate 50x36", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0, u0)
+    sim.step(30)
+    compare(sim, p, oracle_run(p, rho0, [30], u0=u0)[30])
+    sim.close()
+
+
+@pytest.mark.parametrize("scheme", ["improved", "standard"])
+def test_plates_fp32_deviation_storage(scheme):
+    shape = (45, 70)
+    p = runtime.params("D2Q9", 70, 45, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, scheme=scheme, precision="fp32",
+                       walls=PLATES)
+    rho0 = _droplet(shape, "vdW", 0.8, 12.0)
+    print(f"case D2Q9 plates fp32 {scheme} 70x45", flush=True)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(10)
+    f_ref, fl = oracle_run(p, rho0, [10])[10]
+    n = int(np.prod(shape))
+    f = sim.get_f()[:, :n].reshape((-1,) + shape)
+    rho, u, mu = sim.moments()
+    errs = {"f": rel_err(f, f_ref), "rho": rel_err(rho.reshape(shape), fl["rho"]),
+            "u_abs": float((u.reshape((-1,) + shape).cpu() - fl["u"]).abs().max()),
+            "mu_abs": float((mu.reshape(shape).cpu() - fl["mu"]).abs().max())}
+    print("fp32 plates errors", errs, flush=True)
+    assert errs["f"] < 2e-6 and errs["rho"] < 2e-6 and errs["u_abs"] < 2e-6 and errs["mu_abs"] < 2e-6
+    sim.close()
+
+
+def test_plates_every_tile_shape_gives_identical_populations():
+    p = runtime.params("D2Q9", 45, 37, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, walls=PLATES)
+    rho0 = _droplet((37, 45), "vdW", 0.8, 8.0)
+    sim = runtime.LBM(p)
+    outs = []
+    for s in range(sim.num_tile_shapes()):
+        print(f"case plates tile shape {s}", flush=True)
+        sim.set_tile_shape(s)
+        sim.init(rho0)
+        sim.step(7)
+        outs.append(sim.get_f().cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    sim.close()
+
+
+def test_batch_mixes_plates_and_periodic_lattices():
+    specs = [dict(nx=40, ny=36, walls=(0.02, 0.0)), dict(nx=33, ny=50),
+             dict(nx=64, ny=24, walls=(-0.03, 0.04), collision="mrt", tau_e=1.0, tau_s=1.0, tau_q=1.0, nu=0.1)]
+    plist, rhos = [], []
+    for k, sp in enumerate(specs):
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        plist.append(runtime.params("D2Q9", nx, ny, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, **sp))
+        rhos.append(_droplet((ny, nx), "vdW", 0.8, 7.0, seed=k))
+    print("case batch of plate and periodic lattices", flush=True)
+    sim = runtime.LBM(plist)
+    sim.init(np.concatenate([r.ravel() for r in rhos]))
+    sim.step(12)
+    for i, (p, r0) in enumerate(zip(plist, rhos)):
+        compare(sim, p, oracle_run(p, r0, [12])[12], lat_index=i)
+    sim.close()
+
+
+def test_plates_population_round_trip():
+    p = runtime.params("D2Q9", 24, 20, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, walls=PLATES)
+    sim = runtime.LBM(p)
+    sim.init(_droplet((20, 24), "vdW", 0.8, 5.0))
+    sim.step(5)
+    f = sim.get_f().clone()
+    sim.set_f(f)
+    assert torch.equal(sim.get_f(), f)
+    sim.close()
+
+
+def test_unsupported_plate_combinations():
+    L = runtime._lib
+    for kw, code in [(dict(lattice="D3Q19", nz=8), L.LBM_ERR_UNSUPPORTED),
+                     (dict(scheme="standard", force_form="ptensor"), L.LBM_ERR_UNSUPPORTED),
+                     (dict(ny=3), L.LBM_ERR_ARG)]:
+        args = dict(lattice="D2Q9", nx=16, ny=16, nz=1)
+        args.update(kw)
+        lattice, nx, ny, nz = args.pop("lattice"), args.pop("nx"), args.pop("ny"), args.pop("nz")
+        with pytest.raises(L.LBMError) as e:
+            runtime.LBM(runtime.params(lattice, nx, ny, nz, walls=PLATES, **args))
+        assert e.value.code == code
+    from paper_2008_01473_amd.adjoint import Rollout
+    with pytest.raises(ValueError):
+        Rollout(runtime.params("D2Q9", 16, 16, 1, walls=PLATES))
