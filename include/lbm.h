@@ -119,8 +119,14 @@ enum lbm_blowup_bits {
  *                see beyond a plate the mirror image of the fluid (rho, mu, phi u_x
  *                even; phi u_y odd).  x stays periodic.
  *   wall_u_bottom, wall_u_top  plate velocities along x (lattice units)
- * A zero-initialised tail (collision, tau_e, tau_s, tau_q, nu, walls all 0) is
- * BGK on a periodic lattice.
+ *   c0           improved scheme: p_m = (c0 + mu)/3.  0 selects the paper's c0 = 1
+ *                (Sec. III); another value (> 0) is an extension, not the paper's
+ *                method: the force of Eq. 24 depends on grad p_m only and the
+ *                uniform-mu rest state stays a fixed point, while a smaller c0 keeps
+ *                the gas rest population rho - 5 p_m/3 of Eq. 27 positive at lower
+ *                T/T_c.
+ * A zero-initialised tail (collision, tau_e, tau_s, tau_q, nu, walls, c0 all 0)
+ * is the paper's method with BGK on a periodic lattice.
  * All lattices of one batch must share lattice, scheme, force_form, precision;
  * collision and its rates may differ between lattices.
  */
@@ -135,6 +141,7 @@ typedef struct {
     double tau_e, tau_s, tau_q, nu;
     int walls, reserved2;
     double wall_u_bottom, wall_u_top;
+    double c0;
 } lbm_params;
 
 /*

@@ -79,6 +79,7 @@ class Params:
     relaxation: Optional[Sequence[float]] = None   # D2Q9 MRT rates; None => BGK 1/tau
     nu: Optional[float] = None        # D2Q9: constant kinematic viscosity -> per-node tau_v
     walls: Optional[Tuple[float, float]] = None   # D2Q9: plate speeds (bottom, top) along x
+    c0: float = 1.0                   # improved scheme: p_m = (c0 + mu) / 3 (the paper: 1)
     extra: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -121,9 +122,10 @@ def chemical_potential(rho, prm):
     return prm.eos.mu(rho, prm.T) - prm.kappa * _stencil(laplacian, rho, prm)
 
 
-def modified_pressure(mu):
-    """p_m = (1 + mu) / 3, Sec. III."""
-    return (1.0 + mu) / 3.0
+def modified_pressure(mu, c0=1.0):
+    """p_m = (1 + mu) / 3, Sec. III.  c0 != 1 replaces the 1 (an extension, not the
+    paper's method: F of Eq. 24 depends on grad p_m only)."""
+    return (c0 + mu) / 3.0
 
 
 def pressure_tensor(rho, prm):
@@ -155,7 +157,7 @@ def fields(f, prm):
     mu = chemical_potential(rho, prm)
     F = force(rho, mu, prm)
     u = (j + 0.5 * F) / rho                                          # Eq. 12
-    pm = modified_pressure(mu) if prm.scheme == "improved" else rho * CS2
+    pm = modified_pressure(mu, prm.c0) if prm.scheme == "improved" else rho * CS2
     return {"rho": rho, "j": j, "mu": mu, "F": F, "u": u, "pm": pm}
 
 
@@ -358,7 +360,7 @@ def init(rho0, prm, u0=None):
     if u0 is None:
         u0 = torch.zeros((lat.D,) + tuple(rho0.shape), dtype=DT)
     if prm.scheme == "improved":
-        pm = modified_pressure(chemical_potential(rho0, prm))
+        pm = modified_pressure(chemical_potential(rho0, prm), prm.c0)
     else:
         pm = rho0 * CS2
     return equilibrium(rho0, u0, pm, prm)

@@ -27,7 +27,8 @@ class lbm_params(ctypes.Structure):
                 ("rho_ref", c_double), ("pm_ref", c_double),
                 ("collision", c_int), ("reserved", c_int),
                 ("tau_e", c_double), ("tau_s", c_double), ("tau_q", c_double), ("nu", c_double),
-                ("walls", c_int), ("reserved2", c_int), ("wall_u_bottom", c_double), ("wall_u_top", c_double)]
+                ("walls", c_int), ("reserved2", c_int), ("wall_u_bottom", c_double), ("wall_u_top", c_double),
+                ("c0", c_double)]
 
 
 class lbm_diag(ctypes.Structure):

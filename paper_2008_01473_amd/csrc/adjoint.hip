@@ -5,7 +5,7 @@
 // Forward step at a node (all derivatives below are of these formulas):
 //   rho = sum f, j = sum e f (Eq. 12);  mu = mu_EOS(rho) - kappa L rho (Eq. 2)
 //   g = grad_d mu (Eq. 17);  F = (1/3 - rho) g (Eq. 24)  or  grad_d(rho)/3 - rho g (Eq. 13)
-//   u = (j + F/2) / rho (Eq. 12);  p_m = (1 + mu)/3 (improved) or rho/3
+//   u = (j + F/2) / rho (Eq. 12);  p_m = (c0 + mu)/3 (improved; the paper: c0 = 1) or rho/3
 //   phi = rho/3 - p_m, psi_i = phi u_i, d_i = d_i psi_i, C_ii = 3 d_i (Eq. 29)
 //   f*_a = (1 - w) f_a + w feq_a(rho, u, p_m) + (1 - w/2) (G_a(u, F) + C_a(C_xx, C_yy))
 //   f_a(x + e_a, t + 1) = f*_a(x) (Eq. 10)
@@ -204,7 +204,7 @@ __global__ void adj_local(AdjArgs a, int fields_mode) {
     const double w = a.rec.omega, w2 = 1.0 - 0.5 * w;
     const double r = F(a, RHO)[i], ux = F(a, UX)[i], uy = F(a, UY)[i];
     const double Fx = F(a, FX)[i], Fy = F(a, FY)[i];
-    const double pm = a.improved ? (1.0 + F(a, MU)[i]) / 3.0 : r / 3.0;
+    const double pm = a.improved ? (a.rec.c0 + F(a, MU)[i]) / 3.0 : r / 3.0;
     const double php = pm - r / 3.0;
     const double usq = ux * ux + uy * uy;
     double rb = 0, uxb = 0, uyb = 0, pb = 0, fxb = 0, fyb = 0, cxxb = 0, cyyb = 0;
@@ -265,7 +265,7 @@ __global__ void adj_velocity(AdjArgs a) {
     if (a.improved) {
         const double psixb = -ddx(F(a, DXB), n, a.nx);
         const double psiyb = -ddy(F(a, DYB), n, a.nx);
-        const double pm = (1.0 + F(a, MU)[i]) / 3.0;
+        const double pm = (a.rec.c0 + F(a, MU)[i]) / 3.0;
         const double phi = r / 3.0 - pm;
         const double phib = psixb * ux + psiyb * uy;
         uxb += phi * psixb;

@@ -213,6 +213,7 @@ int check_params(const lbm_params& p) {
             return fail(LBM_ERR_ARG, "MRT relaxation times tau_e, tau_s, tau_q must be > 0.5");
         if (!(p.nu == p.nu)) return fail(LBM_ERR_ARG, "nu must be a number");
     }
+    if (!(p.c0 >= 0) || !std::isfinite(p.c0)) return fail(LBM_ERR_ARG, "c0 must be >= 0 (0 selects 1)");
     if (p.walls != 0) {
         if (p.walls != 1) return fail(LBM_ERR_ARG, "walls must be 0 or 1");
         if (p.lattice != LBM_D2Q9) return fail(LBM_ERR_UNSUPPORTED, "plates are implemented for D2Q9");
@@ -240,6 +241,7 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     R.kappa = p.kappa;
     R.omega = 1.0 / p.tau;
     R.rho_max = host::rho_limit(p.eos, p.b);
+    R.c0 = p.c0 > 0 ? p.c0 : 1.0;
     if (p.walls) {
         R.walls = 1;
         R.wall_u0 = p.wall_u_bottom;
@@ -255,7 +257,7 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     if (p.precision == LBM_FP64) {
         R.rho_ref = 0.0;
         R.pm_ref = 0.0;
-        R.mu_ref = -1.0;     // so that p_m - pm_ref = (mu - mu_ref)/3 = p_m
+        R.mu_ref = -R.c0;    // so that p_m - pm_ref = (mu - mu_ref)/3 = p_m
         return R;
     }
     double rho_ref = p.rho_ref, pm_ref = p.pm_ref;
@@ -271,11 +273,11 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
             mm = host::mu_eos(p.eos, p.a, p.b, p.R, T, rr);
         }
         if (!(rho_ref > 0)) rho_ref = rr;
-        if (!(pm_ref > 0)) pm_ref = (variant == kImproved) ? (1.0 + mm) / 3.0 : rho_ref / 3.0;
+        if (!(pm_ref > 0)) pm_ref = (variant == kImproved) ? (R.c0 + mm) / 3.0 : rho_ref / 3.0;
     }
     R.rho_ref = rho_ref;
     R.pm_ref = pm_ref;
-    R.mu_ref = 3.0 * pm_ref - 1.0;
+    R.mu_ref = 3.0 * pm_ref - R.c0;
     if (variant != kImproved) R.pm_ref = rho_ref / 3.0;
     const double pmr = R.pm_ref;
     if (Q == 9) {

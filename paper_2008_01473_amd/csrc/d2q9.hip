@@ -274,7 +274,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     for (int a = 0; a < 9; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
-    const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref;
+    const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
 
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const T ux = (s_a[k] + T(0.5) * Fx) * ir;
         const T uy = (s_b[k] + T(0.5) * Fy) * ir;
         if constexpr (IMP) {
-            const T phi = r * T(1.0 / 3.0) - (T(1) + s_mu[c2]) * T(1.0 / 3.0);           // Eq. 29
+            const T phi = r * T(1.0 / 3.0) - (c0 + s_mu[c2]) * T(1.0 / 3.0);             // Eq. 29
             s_a[k] = phi * ux;
             s_b[k] = phi * uy;
         }
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         } else {
             T dpm, php, Cxx = T(0), Cyy = T(0);
             if constexpr (IMP) {
-                const T pm = (T(1) + mu) * T(1.0 / 3.0);
+                const T pm = (c0 + mu) * T(1.0 / 3.0);
                 dpm = (mu - mu_ref) * T(1.0 / 3.0);
                 php = pm - r * T(1.0 / 3.0);
                 Cxx = T(3) * ddx<W1>(s_a, c1);
@@ -535,7 +535,7 @@ __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const do
         const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
         const T mu = eos.mu(r) - (T)R.kappa * L2;
         dpm = (mu - (T)R.mu_ref) * T(1.0 / 3.0);
-        php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+        php = ((T)R.c0 + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
     } else {
         dpm = (r - (T)R.rho_ref) * T(1.0 / 3.0);
         php = T(0);

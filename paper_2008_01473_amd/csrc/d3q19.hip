@@ -213,7 +213,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     for (int a = 0; a < 19; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
-    const T rho_ref = (T)R.rho_ref, mu_ref = (T)R.mu_ref;
+    const T rho_ref = (T)R.rho_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
     const int x0 = tile.x0, y0 = tile.y0, z0 = tile.z0, zn = tile.zn;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 const T uy = (s_j[3 * A1 + c1] + T(0.5) * Fy) * ir;
                 const T uz = (s_j[6 * A1 + c1] + T(0.5) * Fz) * ir;
                 if constexpr (IMP) {
-                    const T phi = r * T(1.0 / 3.0) - (T(1) + Mp[c2]) * T(1.0 / 3.0);    // Eq. 29
+                    const T phi = r * T(1.0 / 3.0) - (c0 + Mp[c2]) * T(1.0 / 3.0);      // Eq. 29
                     s_psi[c1] = phi * ux;
                     s_psi[3 * A1 + c1] = phi * uy;
                     s_psi[6 * A1 + c1] = phi * uz;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     Cyy = T(3) * gy<W1>(Yd, Yp, Yu, c1);
                     Czz = T(3) * gz<W1>(Zdd, Zp, Zu, c1);
                     dpm = (mu - mu_ref) * T(1.0 / 3.0);
-                    php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+                    php = (c0 + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
                 } else {
                     dpm = drho * T(1.0 / 3.0);
                     php = T(0);
@@ -522,7 +522,7 @@ __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const do
         const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
         const T mu = eos.mu(r) - (T)R.kappa * L2;
         dpm = (mu - (T)R.mu_ref) * T(1.0 / 3.0);
-        php = (T(1) + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+        php = ((T)R.c0 + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
     } else {
         dpm = (r - (T)R.rho_ref) * T(1.0 / 3.0);
         php = T(0);

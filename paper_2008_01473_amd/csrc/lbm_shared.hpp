@@ -41,6 +41,7 @@ struct LatticeRec {
     // D2Q9 plates bounding y (walls != 0): x-velocities of the bottom and top plate.
     int walls, pad_walls;
     double wall_u0, wall_u1;
+    double c0;                          // improved scheme: p_m = (c0 + mu)/3 (the paper: 1)
 };
 
 // One unit of work: an output tile (2D) or an output column chunk (3D).

@@ -24,11 +24,13 @@ EOS_DEFAULTS = {"vdW": (9.0 / 392.0, 2.0 / 21.0), "CS": (0.0282217394824, 0.1490
 
 def params(lattice="D2Q9", nx=64, ny=64, nz=1, eos="vdW", a=None, b=None, R=1.0, T_over_Tc=0.8,
            kappa=0.02, tau=1.0, scheme="improved", force_form="chempot", precision="fp64",
-           rho_ref=0.0, pm_ref=0.0, collision="bgk", tau_e=1.0, tau_s=1.0, tau_q=1.0, nu=0.0, walls=None):
+           rho_ref=0.0, pm_ref=0.0, collision="bgk", tau_e=1.0, tau_s=1.0, tau_q=1.0, nu=0.0, walls=None,
+           c0=1.0):
     """An lbm_params record (see include/lbm.h).  collision="mrt" selects the
     relaxation matrix of Eq. 8 with rates 1/tau_e, 1/tau_s, 1/tau_q and a shear
     rate from tau (nu <= 0) or from a constant kinematic viscosity nu.
-    walls=(U_bottom, U_top) bounds a D2Q9 lattice in y by plates moving along x."""
+    walls=(U_bottom, U_top) bounds a D2Q9 lattice in y by plates moving along x.
+    c0 (improved scheme): p_m = (c0 + mu)/3; the paper's method is c0 = 1."""
     da, db = EOS_DEFAULTS[eos]
     p = lbm_params()
     p.lattice, p.nx, p.ny, p.nz = _LATTICE[lattice], nx, ny, nz
@@ -40,6 +42,7 @@ def params(lattice="D2Q9", nx=64, ny=64, nz=1, eos="vdW", a=None, b=None, R=1.0,
     p.tau_e, p.tau_s, p.tau_q, p.nu = tau_e, tau_s, tau_q, nu
     if walls is not None:
         p.walls, p.wall_u_bottom, p.wall_u_top = 1, float(walls[0]), float(walls[1])
+    p.c0 = c0
     return p
 
 

@@ -29,7 +29,7 @@ MLL = [
 ]
 
 
-def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=None, walls=None):
+def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=None, walls=None, c0=1.0):
     """f: dict {(a, node): value}; dims = (nx, ny) or (nx, ny, nz); node = (x, y[, z]).
     mrt (D2Q9 only): dict(s_e, s_eps, s_q, nu) -> collision in the moment basis MLL
     with rates (1, s_e, s_eps, 1, s_q, 1, s_q, s_v, s_v); s_v = 1/tau if nu is None,
@@ -96,7 +96,7 @@ def step(f, dims, mu_eos, p_eos, kappa, tau, scheme, force_form="chempot", mrt=N
                 div.append(s)
             F[n] = [grh[k] / 3 - div[k] for k in range(D)]
     u = {n: [(j[n][d] + 0.5 * F[n][d]) / rho[n] for d in range(D)] for n in nodes}
-    pm = {n: ((1 + mu[n]) / 3 if scheme == "improved" else rho[n] / 3) for n in nodes}
+    pm = {n: ((c0 + mu[n]) / 3 if scheme == "improved" else rho[n] / 3) for n in nodes}
     dcorr = {}
     if scheme == "improved":
         psi = [{n: (rho[n] / 3 - pm[n]) * u[n][d] for n in nodes} for d in range(D)]

@@ -27,7 +27,7 @@ def oracle_params(p):
     return model.Params(lattice="D2Q9" if p.lattice == 0 else "D3Q19", eos=E, T_over_Tc=p.T_over_Tc,
                         kappa=p.kappa, tau=p.tau, scheme="improved" if p.scheme == 1 else "standard",
                         force_form="ptensor" if p.force_form == 1 else "chempot", relaxation=relaxation, nu=nu,
-                        walls=(p.wall_u_bottom, p.wall_u_top) if p.walls else None)
+                        walls=(p.wall_u_bottom, p.wall_u_top) if p.walls else None, c0=p.c0 if p.c0 > 0 else 1.0)
 
 
 def shape_of(p):

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(lbm_params) == 168
+    assert ctypes.sizeof(lbm_params) == 176
     assert ctypes.sizeof(lib_mod.lbm_diag) == 72
 
 

@@ -24,20 +24,20 @@ from paper_2008_01473_amd.adjoint import Rollout, rollout  # noqa: E402
 def _oracle_params(p, kappa, T):
     E = oeos.make_eos(EOS_NAMES[p.eos], p.a, p.b, p.R)
     return model.Params(lattice="D2Q9", eos=E, T_over_Tc=T, kappa=kappa, tau=p.tau,
-                        scheme="improved" if p.scheme == 1 else "standard")
+                        scheme="improved" if p.scheme == 1 else "standard", c0=p.c0 if p.c0 > 0 else 1.0)
 
 
-def _case(scheme, n=(20, 24), T=0.8, kappa=0.02, tau=0.8, seed=0):
+def _case(scheme, n=(20, 24), T=0.8, kappa=0.02, tau=0.8, seed=0, c0=1.0):
     ny, nx = n
-    p = runtime.params("D2Q9", nx, ny, 1, eos="vdW", T_over_Tc=T, kappa=kappa, tau=tau, scheme=scheme)
+    p = runtime.params("D2Q9", nx, ny, 1, eos="vdW", T_over_Tc=T, kappa=kappa, tau=tau, scheme=scheme, c0=c0)
     m = oeos.maxwell(oeos.VanDerWaals(), T)
     rho0 = inputs.droplet((ny, nx), m["rho_g"], m["rho_l"], 5.0, 5.0, noise=1e-3, seed=seed)
     return p, rho0
 
 
-@pytest.mark.parametrize("scheme", ["improved", "standard"])
-def test_adjoint_step_matches_oracle_autograd(scheme):
-    p, rho0 = _case(scheme)
+@pytest.mark.parametrize("scheme,c0", [("improved", 1.0), ("standard", 1.0), ("improved", 0.7)])
+def test_adjoint_step_matches_oracle_autograd(scheme, c0):
+    p, rho0 = _case(scheme, c0=c0)
     shape = shape_of(p)
     kap = torch.tensor(0.02, dtype=torch.float64, requires_grad=True)
     tt = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
