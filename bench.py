@@ -17,8 +17,9 @@ shape, read from the `traffic-record:` lines of profiles/*.md; null when no
 record matches the current kernel sources (SHA-256 over the csrc directory).
 `cpu_baseline`: the CPU oracle on a bounded number of steps of the same lattice.
 `secondary`: the same measurement for FP32 deviation storage, the MRT collision
-at constant viscosity, the standard scheme, the 256^3 D3Q19 droplet, 4096^2
-lattices and a batched coexistence sweep, plus the adjoint's cost.
+at constant viscosity, moving plates, the p_m offset at T/Tc = 0.7, the standard
+scheme, the 256^3 D3Q19 droplet, 4096^2 lattices and a batched coexistence
+sweep, plus the adjoint's cost.
 """
 
 import argparse
@@ -165,6 +166,28 @@ def mrt_spec(runtime, inputs, nu=0.15):
                         f"scheme, MRT (Eq. 8) tau_e = tau_s = tau_q = 1, constant nu = {nu}, fp64"}
 
 
+def plates_spec(runtime, inputs):
+    """The primary's droplet in a channel: plates at y = -1/2 and 511.5 moving at
+    +0.05 and -0.05 along x (halfway bounce-back), improved scheme, fp64."""
+    m = runtime.maxwell("CS", 0.8)
+    p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8, walls=(-0.05, 0.05))
+    rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
+    return {"name": "d2q9_512_cs_improved_plates_fp64", "params": [p], "rho0": rho0,
+            "workload": "D2Q9 512x512, periodic in x, plates moving at -0.05 / +0.05 bounding y, Carnahan-Starling "
+                        "droplet r=80 W=5, T/Tc=0.8, kappa=0.01, tau=0.8, improved scheme, fp64"}
+
+
+def c0_spec(runtime, inputs):
+    """vdW droplet at T/Tc = 0.7 with the p_m offset c0 = 0.6 (an extension that keeps
+    the gas rest population positive; the paper's c0 = 1 blows up here), fp64."""
+    m = runtime.maxwell("vdW", 0.7)
+    p = runtime.params("D2Q9", 512, 512, 1, eos="vdW", T_over_Tc=0.7, kappa=0.02, tau=1.0, c0=0.6)
+    rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
+    return {"name": "d2q9_512_vdw_improved_c0_fp64", "params": [p], "rho0": rho0,
+            "workload": "D2Q9 512x512 periodic, van der Waals droplet r=80 W=5, T/Tc=0.7, kappa=0.02, tau=1, "
+                        "improved scheme with p_m = (0.6 + mu)/3, fp64"}
+
+
 def d2q9_large_spec(runtime, inputs, precision="fp64", n=4096):
     """The primary's physics on a lattice large enough to leave the launch-latency
     regime: n x n CS droplet of radius 80 n / 512."""
@@ -225,7 +248,11 @@ def adjoint_measure(torch, runtime, inputs, n_steps=4000):
     r0 = torch.as_tensor(rho0).reshape(-1).cuda().requires_grad_(True)
     kd = torch.tensor(0.02, dtype=torch.float64, device="cuda", requires_grad=True)
     td = torch.tensor(0.75, dtype=torch.float64, device="cuda", requires_grad=True)
-    roll.forward(r0.detach(), 0.02, 0.75, 64)          # warm-up (graph capture)
+    # warm-up: a whole forward and backward, so that graph capture and the first
+    # allocation of the checkpoint and segment buffers stay out of the timing
+    rho_w, u_w = rollout(r0, kd, td, roll, n_steps)
+    (((rho_w - tgt) ** 2).sum() + (u_w ** 2).sum()).backward()
+    r0.grad, kd.grad, td.grad = None, None, None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rho_n, u_n = rollout(r0, kd, td, roll, n_steps)
@@ -307,6 +334,8 @@ def main():
         jobs = [
             ("fp32", lambda: primary_spec(runtime, inputs, precision="fp32"), args.steps),
             ("mrt", lambda: mrt_spec(runtime, inputs), args.steps),
+            ("plates", lambda: plates_spec(runtime, inputs), args.steps),
+            ("c0", lambda: c0_spec(runtime, inputs), args.steps),
             # the standard scheme blows up for this droplet at T/Tc = 0.8 (oracle too); 0.9 is stable
             ("standard", lambda: primary_spec(runtime, inputs, scheme="standard", T=0.9), args.steps),
             ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),
