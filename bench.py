@@ -272,6 +272,26 @@ def adjoint_measure(torch, runtime, inputs, n_steps=4000):
             "grad_kappa": float(kd.grad), "grad_T_over_Tc": float(td.grad)}
 
 
+def copy_ceiling(torch, runtime, mib=2048, reps=10):
+    """Device-to-device bandwidth of the library's plain copy kernel (read + write
+    bytes over the event-timed duration): the achievable side of the HBM roofline."""
+    nbytes = mib * 2**20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    runtime.copy_kernel(dst, src, nbytes, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        runtime.copy_kernel(dst, src, nbytes, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "bytes_per_launch": 2 * nbytes,
+            "kernel": "lbm_copy_kernel (16-byte vector loads and stores, grid-stride)"}
+
+
 def cpu_baseline(torch, inputs, seconds):
     """The oracle (float64, CPU) on the primary lattice, as many whole steps as fit
     in about `seconds` (at least 2)."""
@@ -363,6 +383,9 @@ def main():
             secondary.append(r)
             print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s)",
                   file=sys.stderr, flush=True)
+    ceiling = copy_ceiling(torch, runtime)
+    print(f"[bench] copy ceiling: {ceiling['GB/s']:.0f} GB/s ({ceiling['frac_of_peak'] * 100:.1f}% of 8 TB/s)",
+          file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(torch, inputs, args.cpu_seconds)
@@ -382,6 +405,7 @@ def main():
         "config": {"workload": prim["workload"], "lattice": "D2Q9", "nodes": prim["nodes"],
                    "bytes_per_lup": prim["bytes_per_lup"], "tile": prim["tile"]},
         "roofline": prim["roofline"],
+        "copy_ceiling": ceiling,
         "cpu_baseline": cpu,
         "secondary": secondary,
     }

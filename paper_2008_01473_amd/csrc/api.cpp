@@ -115,7 +115,7 @@ struct lbm_ctx {
     int zchunk_for(int s) const;
     std::vector<Tile> plan(int s, std::vector<LatticeRec>& rr) const;
     void drop_graphs() {
-        for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);   // teardown: nothing to report
         graphs.clear();
     }
 };
@@ -367,13 +367,13 @@ int graph_for(lbm_ctx* h, int n, hipGraphExec_t* out) {
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     h->cur = saved;
     if (rc != LBM_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     h->graphs[key] = ex;
     *out = ex;
@@ -716,8 +716,8 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
         HIP_TRY(hipMemcpyAsync(h->buf[h->cur], scratch, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
         h->t = t0;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != LBM_OK) return rc;
     rc = lbm_set_tile_shape(h, best);
     if (rc != LBM_OK) return rc;
@@ -807,7 +807,7 @@ int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream) 
 void lbm_destroy(lbm_ctx* h) {
     if (!h) return;
     h->drop_graphs();
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
 

@@ -51,10 +51,22 @@ __global__ __launch_bounds__(256) void finalize_diag_kernel(const DiagPartial* p
     }
 }
 
-__global__ void copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Plain copy: each thread moves four 16-byte vectors per pass (all loads issued
+// before the stores), stores non-temporal like the step kernels' population stores.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+__global__ void copy_kernel(uint4* __restrict__ dst_, const uint4* __restrict__ src_, size_t n16) {
+    v4u* __restrict__ dst = reinterpret_cast<v4u*>(dst_);
+    const v4u* __restrict__ src = reinterpret_cast<const v4u*>(src_);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n16; i += stride) dst[i] = src[i];
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const v4u a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(src[i], dst + i);
 }
 
 __global__ void zero_u32_kernel(unsigned* p, int n) {

@@ -287,15 +287,20 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     T fh[HP][9];
     int hpos[HP];
     const bool plates = PLATES && R.walls;
+    // A tile whose pulls (tile + 4 rings) stay inside the lattice needs no periodic
+    // wrap: block-uniform, so the wrap arithmetic is skipped for most tiles.
+    const bool inner = x0 >= 4 && x0 + BX + 4 <= nx && y0 >= 4 && y0 + BY + 4 <= ny;
+    auto wx = [&](int v) { return inner ? v : wrap(v, nx, sx); };
+    auto wy = [&](int v) { return inner ? v : wrap(v, ny, sy); };
     bool own_mirror = false;
     bool h_mirror[HP];
     {
         const int gx = x0 + lx0, gy = y0 + ly0;
-        const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
+        const int xc = wx(gx), xm = wx(gx - 1), xp = wx(gx + 1);
         if (plates) {
             pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, own_mirror), fown);
         } else {
-            const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+            const int yc = wy(gy), ym = wy(gy - 1), yp = wy(gy + 1);
             pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown);
         }
     }
@@ -317,13 +322,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         }
         hpos[q] = ly * W3 + lx;
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
-        const int xc = wrap(gx, nx, sx), xm = wrap(gx - 1, nx, sx), xp = wrap(gx + 1, nx, sx);
+        const int xc = wx(gx), xm = wx(gx - 1), xp = wx(gx + 1);
         h_mirror[q] = false;
         if ((tid & ~63) + q * NT < HALO) {            // waves with no halo node left skip the pulls
             if (plates) {
                 pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, h_mirror[q]), fh[q]);
             } else {
-                const int yc = wrap(gy, ny, sy), ym = wrap(gy - 1, ny, sy), yp = wrap(gy + 1, ny, sy);
+                const int yc = wy(gy), ym = wy(gy - 1), yp = wy(gy + 1);
                 pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fh[q]);
             }
         }
