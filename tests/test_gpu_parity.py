@@ -356,3 +356,44 @@ def test_standard_scheme_droplet_instability_is_flagged():
         sim.close()
     assert res["standard"]["status"] != 0
     assert res["improved"]["status"] == 0 and res["improved"]["max_u"] < 1e-2
+
+
+def test_full_size_batch96_sampled_lattices():
+    """The 96-lattice coexistence sweep exactly as the benchmark builds and tunes it
+    (seeded sizes 64^2-512^2, slabs and droplets, T/Tc in [0.5, 0.95], float32, one
+    launch per step): after 4 graph-replayed steps, one lattice of every size is
+    compared with the float64 oracle at float32 round-off, and every lattice's mass
+    sum against its initial mass."""
+    import importlib.util
+    import os
+    spec_b = importlib.util.spec_from_file_location(
+        "bench", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py"))
+    bench = importlib.util.module_from_spec(spec_b)
+    spec_b.loader.exec_module(bench)
+    spec = bench.batch_spec(runtime, inputs)
+    plist, rho0 = spec["params"], spec["rho0"]
+    print(f"case full-size batch of {len(plist)} lattices, {rho0.size} nodes", flush=True)
+    sim = runtime.LBM(plist)
+    sim.init(rho0)
+    sim.autotune(4)
+    sim.step(4)
+    rho, u, _ = sim.moments()
+    diag = sim.diagnostics()
+    offs = sim.offsets()
+    picked = {}
+    for i, p in enumerate(plist):
+        picked.setdefault(p.nx, i)
+    for n, i in sorted(picked.items()):
+        p = plist[i]
+        shape = (p.ny, p.nx)
+        r0 = rho0[offs[i]:offs[i] + p.nx * p.ny].reshape(shape)
+        f_ref, fl = oracle_run(p, r0, [4])[4]
+        r = rho[offs[i]:offs[i] + p.nx * p.ny].reshape(shape)
+        e_rho = rel_err(r, fl["rho"])
+        print(f"  lattice {i} n={n}: rel err rho {e_rho:.2e}", flush=True)
+        assert diag[i]["status"] == 0 and e_rho < 2e-6
+    for i, p in enumerate(plist):
+        m0 = float(np.sum(rho0[offs[i]:offs[i] + p.nx * p.ny]))
+        if diag[i]["status"] == 0:
+            assert diag[i]["mass"] == pytest.approx(m0, rel=1e-6)
+    sim.close()
