@@ -254,6 +254,16 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
                      double* grad);
 int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar,
                        double* lam_out, void* ws, double* grad);
+/* lbm_adjoint_segment: one checkpoint segment of a checkpointed backward pass.
+ * Restores `checkpoint` (raw state of time level t0, lbm_get_state layout) into
+ * the handle, recomputes the m >= 1 states of time levels t0 .. t0+m-1 into
+ * `states` (device, m * lbm_state_bytes, caller-owned, overwritten), then runs
+ * lbm_adjoint_step from t0+m-1 down to t0.  On entry lam holds dL/df(t0+m), on
+ * exit dL/df(t0) (layout of lbm_get_f); lam2 is device scratch of the same size
+ * (must not alias lam); grad is incremented as by lbm_adjoint_step.  The handle is
+ * left at time level t0 + m with no diagnostics.  Same support as the calls above. */
+int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m, void* states, double* lam,
+                        double* lam2, void* ws, double* grad);
 int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double* grad_rho0, void* ws,
                      double* grad);
 

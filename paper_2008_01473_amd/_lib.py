@@ -62,6 +62,8 @@ SIGNATURES = {
     "lbm_critical_temperature": (c_double, [c_int, c_double, c_double, c_double]),
     "lbm_set_physics": (c_int, [c_void_p, c_int, c_double, c_double]),
     "lbm_adjoint_workspace_bytes": (c_size_t, [c_void_p]),
+    "lbm_adjoint_segment": (c_int, [c_void_p, c_void_p, c_longlong, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p]),
     "lbm_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_init": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

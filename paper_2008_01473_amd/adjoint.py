@@ -9,9 +9,10 @@ adjoint kernels and sqrt(N) checkpointing of the forward states.
 
 Forward: lbm_init, then n steps; the raw state is checkpointed every k = ceil(sqrt(n))
 steps.  Backward: dL/df(N) from lbm_adjoint_fields, then segment by segment in
-reverse: restore the checkpoint, recompute and keep the segment's states, run
-lbm_adjoint_step back through them; finally lbm_adjoint_init gives dL/drho0.
-All of this runs in the HIP kernels; this module orders the calls.
+reverse lbm_adjoint_segment (restore the checkpoint, recompute and keep the
+segment's states, run the adjoint steps back through them); finally
+lbm_adjoint_init gives dL/drho0.  All of this runs in the HIP kernels and the
+library's runtime; this module orders the calls.
 """
 
 import math
@@ -72,17 +73,11 @@ class Rollout:
         check(L.lbm_adjoint_fields(sim.h, self.final_state.data_ptr(), None if rb is None else rb.data_ptr(),
                                    None if ub is None else ub.data_ptr(), lam.data_ptr(), ws, grad.data_ptr()),
               "lbm_adjoint_fields")
+        states = torch.empty(self.k * sim.state_bytes, dtype=torch.uint8, device=dev)
         for t0 in sorted(self.checkpoints, reverse=True):
             m = min(self.k, self.n - t0)
-            sim.set_state(self.checkpoints[t0], t0)
-            seg = []
-            for _ in range(m):
-                seg.append(sim.get_state()[0])
-                sim.step(1)
-            for s in reversed(seg):
-                check(L.lbm_adjoint_step(sim.h, s.data_ptr(), lam.data_ptr(), lam2.data_ptr(), ws, grad.data_ptr()),
-                      "lbm_adjoint_step")
-                lam, lam2 = lam2, lam
+            check(L.lbm_adjoint_segment(sim.h, self.checkpoints[t0].data_ptr(), t0, m, states.data_ptr(),
+                                        lam.data_ptr(), lam2.data_ptr(), ws, grad.data_ptr()), "lbm_adjoint_segment")
         grad_rho0 = torch.empty(self.N, dtype=torch.float64, device=dev)
         check(L.lbm_adjoint_init(sim.h, self.rho0.data_ptr(), lam.data_ptr(), grad_rho0.data_ptr(), ws,
                                  grad.data_ptr()), "lbm_adjoint_init")

@@ -366,16 +366,22 @@ __global__ void adj_init_local(AdjArgs a) {
     }
 }
 
-// Sum the block partials in order and add them to the two accumulators.
+// Sum the block partials and add them to the two accumulators: one wave, lane l
+// summing blocks l, l + 64, ... in order, then a fixed butterfly across the lanes,
+// so that every run adds in the same order.
 __global__ void adj_reduce(const double* partial, int nblocks, double* grad) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int lane = threadIdx.x;
     double k = 0, t = 0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = lane; b < nblocks; b += 64) {
         k += partial[2 * b];
         t += partial[2 * b + 1];
     }
-    grad[0] += k;
-    grad[1] += t;
+    k = wave_sum(k);
+    t = wave_sum(t);
+    if (lane == 0) {
+        grad[0] += k;
+        grad[1] += t;
+    }
 }
 
 }  // namespace adj

@@ -776,6 +776,40 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
     return LBM_OK;
 }
 
+int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m, void* states, double* lam,
+                        double* lam2, void* ws, double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!checkpoint || !states || !lam || !lam2 || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
+    if (m < 1) return fail(LBM_ERR_ARG, "m must be >= 1");
+    if (lam == lam2) return fail(LBM_ERR_ARG, "lam and lam2 must not alias");
+    rc = lbm_set_state(h, checkpoint, t0);
+    if (rc != LBM_OK) return rc;
+    char* st = reinterpret_cast<char*>(states);
+    // recompute the segment's states t0 .. t0 + m - 1 (no diagnostics needed)
+    for (int k = 0; k < m; ++k) {
+        HIP_TRY(hipMemcpyAsync(st + (size_t)k * h->state_bytes, h->buf[h->cur], h->state_bytes,
+                               hipMemcpyDeviceToDevice, h->stream));
+        rc = enqueue_steps(h, 1, h->stream, kStep);
+        if (rc != LBM_OK) return rc;
+    }
+    h->t = t0 + m;
+    h->t_diag = -1;
+    // back through them: dL/df(t) from dL/df(t + 1)
+    double* in = lam;
+    double* out = lam2;
+    for (int k = m - 1; k >= 0; --k) {
+        HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved,
+                               st + (size_t)k * h->state_bytes, in, out, nullptr, nullptr, nullptr, nullptr,
+                               reinterpret_cast<double*>(ws), grad, h->stream));
+        std::swap(in, out);
+    }
+    if (in != lam)
+        HIP_TRY(hipMemcpyAsync(lam, in, (size_t)9 * h->recs[0].nnodes * sizeof(double), hipMemcpyDeviceToDevice,
+                               h->stream));
+    return LBM_OK;
+}
+
 int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar, double* lam_out,
                        void* ws, double* grad) {
     int rc = adjoint_check(h);

@@ -227,3 +227,40 @@ def test_full_size_adjoint_config_against_finite_differences():
           flush=True)
     assert max(errs64) < 1e-5
     assert max(errs32) < 1e-2
+
+
+@pytest.mark.parametrize("m", [1, 5])
+def test_adjoint_segment_equals_step_by_step(m):
+    """lbm_adjoint_segment (restore, recompute m states, m adjoint steps) gives
+    the same lambda and parameter gradients as doing it call by call."""
+    p, rho0 = _case("improved")
+    roll = Rollout(p)
+    sim = roll.sim
+    L = _lib.lib()
+    sim.init(rho0)
+    sim.step(3)
+    ck, t0 = sim.get_state()
+    lam0 = torch.randn(9 * sim.N, dtype=torch.float64, generator=torch.Generator().manual_seed(5)).cuda()
+    # call by call
+    sim.set_state(ck, t0)
+    seg = []
+    for _ in range(m):
+        seg.append(sim.get_state()[0])
+        sim.step(1)
+    lam, lam2 = lam0.clone(), torch.empty_like(lam0)
+    g1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for s in reversed(seg):
+        _lib.check(L.lbm_adjoint_step(sim.h, s.data_ptr(), lam.data_ptr(), lam2.data_ptr(), roll.ws.data_ptr(),
+                                      g1.data_ptr()))
+        lam, lam2 = lam2, lam
+    # one call
+    states = torch.empty(m * sim.state_bytes, dtype=torch.uint8, device="cuda")
+    lam_b, lam_b2 = lam0.clone(), torch.empty_like(lam0)
+    g2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    _lib.check(L.lbm_adjoint_segment(sim.h, ck.data_ptr(), t0, m, states.data_ptr(), lam_b.data_ptr(),
+                                     lam_b2.data_ptr(), roll.ws.data_ptr(), g2.data_ptr()))
+    torch.cuda.synchronize()
+    assert torch.equal(lam_b, lam)
+    assert torch.equal(g1, g2)
+    assert sim.time == t0 + m
+    roll.close()
