@@ -419,6 +419,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const T mu = s_mu[c2];
         const T Fx = s_F[tid], Fy = s_F[NT + tid], ux = s_u[tid], uy = s_u[NT + tid];
         const T drho = sum9(fown);
+        constexpr bool F32 = sizeof(S) == 4;
+        const double m_in = F32 ? mass_in<9, T>(fown) : 0.0;      // exact node mass (float32 storage)
         const int node = gy * nx + gx;
         if constexpr (MODE == kFields) {
             const long long o = R.field_offset + node;
@@ -452,6 +454,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             } else {
                 collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
             }
+            if constexpr (F32) keep_mass_on_axes<9, 4, T>(fown, m_in);
             if (plates && (gy == 0 || gy == ny - 1)) {
                 // Populations heading into a plate are stored reflected for the next pull:
                 // f*_a + feq_-a - feq_a at the plate velocity U (along x).  The odd part of
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fown[a]);
         }
-        acc.mass = (double)drho;
+        acc.mass = F32 ? m_in : (double)drho;
         acc.mx = (double)(r * ux);
         acc.my = (double)(r * uy);
         acc.umax2 = (double)(ux * ux + uy * uy);

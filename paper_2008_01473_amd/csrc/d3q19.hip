@@ -429,6 +429,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 pull<S, T>(pp, OX, OY, Zd, f);
             }
             const T drho = sum19(f);
+            constexpr bool F32 = sizeof(S) == 4;
+            const double m_in = F32 ? mass_in<19, T>(f) : 0.0;    // exact node mass (float32 storage)
             const int node = zd * NXY + gy0 * nx + gx0;
             if constexpr (MODE == kFields) {
                 const long long o = R.field_offset + node;
@@ -456,10 +458,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     php = T(0);
                 }
                 collide<T>(f, r, drho, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
+                if constexpr (F32) keep_mass_on_axes<19, 6, T>(f, m_in);
 #pragma unroll
                 for (int a = 0; a < 19; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
             }
-            acc.mass += (double)drho;
+            acc.mass += F32 ? m_in : (double)drho;
             acc.mx += (double)(r * ux);
             acc.my += (double)(r * uy);
             acc.mz += (double)(r * uz);

@@ -391,7 +391,10 @@ def test_full_size_batch96_sampled_lattices():
         r = rho[offs[i]:offs[i] + p.nx * p.ny].reshape(shape)
         e_rho = rel_err(r, fl["rho"])
         print(f"  lattice {i} n={n}: rel err rho {e_rho:.2e}", flush=True)
-        assert diag[i]["status"] == 0 and e_rho < 2e-6
+        # float32 round-off: 2e-7 - 4e-7 on most lattices; the 512^2 one (T/Tc 0.52,
+        # kappa 0.005, the sweep's stiffest) amplifies it to 2.9e-6, about twice its value
+        # before each node's rounding remainder was kept on its axis populations (mass-exact)
+        assert diag[i]["status"] == 0 and e_rho < 5e-6
     for i, p in enumerate(plist):
         m0 = float(np.sum(rho0[offs[i]:offs[i] + p.nx * p.ny]))
         if diag[i]["status"] == 0:
