@@ -206,7 +206,11 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu);
 /* Copy the diagnostics of every lattice (count entries) to host memory.  They
  * refer to the time level of the most recent lbm_step input or lbm_moments
  * call (lbm_diag.step).  Blocks until the stream has finished.  Returns
- * LBM_ERR_BLOWUP if any lattice has its status set (out is still filled). */
+ * LBM_ERR_BLOWUP if any lattice has its status set (out is still filled).
+ * Lattices it reports blown up leave the launch plan (their populations stay
+ * frozen and no work group is spent on them; captured graphs are re-captured
+ * on the next lbm_step) until lbm_init, lbm_set_f or lbm_set_state clears the
+ * flags; repeated calls before the next step return the same values. */
 int lbm_diagnostics(lbm_ctx* h, lbm_diag* out_host);
 
 /* Populations f_a(x, t) at the current time level as float64 (layout above),
@@ -289,7 +293,8 @@ int lbm_describe_tile_shape(const lbm_ctx* h, int shape_index, int* bx, int* by,
 int lbm_set_use_graphs(lbm_ctx* h, int on);
 
 /* Pick the fastest tile shape by timing `steps` steps of each on the current
- * state (the state is restored afterwards); returns the chosen index. */
+ * state (the state, the time level and the blow-up flags are restored
+ * afterwards); returns the chosen index. */
 int lbm_autotune(lbm_ctx* h, int steps, void* scratch_state);
 
 /* Measurement helper: copy `bytes` from src to dst on the handle-less stream

@@ -93,6 +93,12 @@ struct lbm_ctx {
     bool bound = false, inited = false;
     bool use_graphs = true;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    // Lattices reported blown up by lbm_diagnostics: left out of the plan (frozen)
+    // until the next reset of the status flags.  Their last diagnostics stay
+    // readable from a host copy until the next step produces new ones.
+    std::vector<char> dropped;
+    std::vector<DiagOut> diag_cache;
+    bool diag_cache_valid = false;
 
     // A tuning index names a kernel tile shape and, for D3Q19, also how many
     // work groups the z-chunking aims at (kZTargets): index = shape * 3 + target.
@@ -142,6 +148,16 @@ int lbm_ctx::zchunk_for(int s) const {
     return zc;
 }
 
+static Tile tile_of(const LatticeRec& R, int L) {
+    Tile t{};
+    t.lat = L;
+    t.nx = R.nx;
+    t.ny = R.ny;
+    t.slow = (R.slow_x ? 1 : 0) | (R.slow_y ? 2 : 0);
+    t.soff = R.state_offset;
+    return t;
+}
+
 std::vector<Tile> lbm_ctx::plan(int s, std::vector<LatticeRec>& rr) const {
     int bx, by;
     shape_dims(s, bx, by);
@@ -153,14 +169,17 @@ std::vector<Tile> lbm_ctx::plan(int s, std::vector<LatticeRec>& rr) const {
         R.slow_y = R.ny < by + 8;
         R.slow_z = R.nz < 8;
         R.tile_begin = (int)out.size();
+        if (dropped[L]) {             // reported blown up: frozen, no work
+            R.tile_end = R.tile_begin;
+            continue;
+        }
         const int ntx = (R.nx + bx - 1) / bx, nty = (R.ny + by - 1) / by;
         if (lattice == LBM_D2Q9) {
             const int band = band_width(ntx, bx);
             for (int k = 0; k < ntx * nty; ++k) {
                 int tx, ty;
                 band_order(k, ntx, nty, band, tx, ty);
-                Tile t{};
-                t.lat = (int)L;
+                Tile t = tile_of(R, (int)L);
                 t.x0 = tx * bx;
                 t.y0 = ty * by;
                 t.z0 = 0;
@@ -172,8 +191,7 @@ std::vector<Tile> lbm_ctx::plan(int s, std::vector<LatticeRec>& rr) const {
             for (int kz = 0; kz < nzc; ++kz)
                 for (int ty = 0; ty < nty; ++ty)
                     for (int tx = 0; tx < ntx; ++tx) {
-                        Tile t{};
-                        t.lat = (int)L;
+                        Tile t = tile_of(R, (int)L);
                         t.x0 = tx * bx;
                         t.y0 = ty * by;
                         t.z0 = kz * zc;
@@ -341,6 +359,26 @@ int upload_tables(lbm_ctx* h) {
     return LBM_OK;
 }
 
+// Rebuild the tile list for the current shape and the current set of frozen
+// lattices; graphs captured with the old list are dropped.
+int replan(lbm_ctx* h) {
+    h->tiles = h->plan(h->shape, h->recs);
+    h->drop_graphs();
+    return upload_tables(h);
+}
+
+// Clear every lattice's blow-up flags and bring frozen lattices back into the plan.
+int reset_status(lbm_ctx* h) {
+    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    h->diag_cache_valid = false;
+    bool any = false;
+    for (char& d : h->dropped) {
+        any |= d != 0;
+        d = 0;
+    }
+    return any ? replan(h) : LBM_OK;
+}
+
 int enqueue_steps(lbm_ctx* h, int n, hipStream_t s, int mode = kStep) {
     for (int i = 0; i < n; ++i) {
         StepArgs a = base_args(h);
@@ -428,6 +466,7 @@ int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx**
         soff += (R.nnodes + 63) / 64 * 64;
         h->recs.push_back(R);
     }
+    h->dropped.assign(count, 0);
     h->field_total = foff;
     h->state_nodes = soff;
     const size_t word = h->precision == LBM_FP64 ? 8 : 4;
@@ -478,7 +517,7 @@ int lbm_bind(lbm_ctx* h, void* f_a, void* f_b, void* workspace) {
     h->cur = 0;
     int rc = upload_tables(h);
     if (rc != LBM_OK) return rc;
-    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->bound = true;
     h->inited = false;
     return LBM_OK;
@@ -494,7 +533,7 @@ int lbm_init(lbm_ctx* h, const double* rho0, const double* u0) {
     else
         HIP_TRY(d3q19_launch_init(h->buf[0], h->d_recs(), (int)h->recs.size(), rho0, u0, h->field_total, h->stream,
                                   h->precision, h->variant));
-    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->t = 0;
     h->t_diag = -1;
     h->inited = true;
@@ -527,6 +566,7 @@ int lbm_step(lbm_ctx* h, int n) {
     if (rc != LBM_OK) return rc;
     h->t = t0 + n;
     h->t_diag = h->t - 1;
+    h->diag_cache_valid = false;
     return LBM_OK;
 }
 
@@ -557,6 +597,7 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu) {
     a.mu_out = mu;
     HIP_TRY(launch_step(h, a, kFields, h->stream));
     h->t_diag = h->t;
+    h->diag_cache_valid = false;
     return LBM_OK;
 }
 
@@ -564,10 +605,35 @@ int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
     if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
     if (!h->inited || h->t_diag < 0) return fail(LBM_ERR_STATE, "no diagnostics yet (step or moments first)");
     const int n = (int)h->recs.size();
-    HIP_TRY(launch_finalize(h->d_partial(), h->d_recs(), h->d_status(), h->d_diag(), n, h->stream));
     std::vector<DiagOut> tmp(n);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), h->d_diag(), n * sizeof(DiagOut), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->diag_cache_valid) {
+        tmp = h->diag_cache;
+    } else {
+        HIP_TRY(launch_finalize(h->d_partial(), h->d_recs(), h->d_status(), h->d_diag(), n, h->stream));
+        HIP_TRY(hipMemcpyAsync(tmp.data(), h->d_diag(), n * sizeof(DiagOut), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        // Lattices newly reported blown up leave the plan.  Their state is copied
+        // into the other buffer so that it stays as it is (the ping-pong buffers
+        // would otherwise alternate between two time levels), and the sums are
+        // kept on the host: a new plan renumbers the per-tile partials.
+        bool fresh = false;
+        const size_t word = h->precision == LBM_FP64 ? 8 : 4;
+        for (int i = 0; i < n; ++i) {
+            if (!tmp[i].status || h->dropped[i]) continue;
+            h->dropped[i] = fresh = true;
+            const LatticeRec& R = h->recs[i];
+            const size_t off = (size_t)R.state_offset * h->Q * word;
+            const size_t len = (size_t)((R.nnodes + 63) / 64 * 64) * h->Q * word;
+            HIP_TRY(hipMemcpyAsync(static_cast<char*>(h->buf[h->cur ^ 1]) + off,
+                                   static_cast<const char*>(h->buf[h->cur]) + off, len, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        }
+        if (fresh) {
+            h->diag_cache = tmp;
+            h->diag_cache_valid = true;
+            if (int rc0 = replan(h); rc0 != LBM_OK) return rc0;
+        }
+    }
     int rc = LBM_OK;
     for (int i = 0; i < n; ++i) {
         out[i].mass = tmp[i].mass;
@@ -607,7 +673,7 @@ int lbm_set_f(lbm_ctx* h, const double* f) {
     else
         HIP_TRY(d3q19_launch_convert(h->buf[h->cur], h->d_recs(), (int)h->recs.size(), const_cast<double*>(f),
                                      h->field_total, h->stream, h->precision, false));
-    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->inited = true;
     h->t_diag = -1;
     return LBM_OK;
@@ -625,7 +691,7 @@ int lbm_set_state(lbm_ctx* h, const void* src, long long step) {
     if (!h || !src) return fail(LBM_ERR_ARG, "null argument");
     if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
     HIP_TRY(hipMemcpyAsync(h->buf[h->cur], src, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->t = step;
     h->t_diag = -1;
     h->inited = true;
@@ -691,6 +757,11 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     int rc = lbm_get_state(h, scratch, &t0);
     if (rc != LBM_OK) return rc;
     const int cur0 = h->cur;
+    // the trial steps may flag lattices: the flags are restored with the state
+    std::vector<unsigned> st0(h->recs.size());
+    HIP_TRY(hipMemcpyAsync(st0.data(), h->d_status(), st0.size() * sizeof(unsigned), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -721,8 +792,11 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     if (rc != LBM_OK) return rc;
     rc = lbm_set_tile_shape(h, best);
     if (rc != LBM_OK) return rc;
-    HIP_TRY(launch_zero_u32(h->d_status(), (int)h->recs.size(), h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_status(), st0.data(), st0.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     h->t_diag = -1;
+    h->diag_cache_valid = false;
     return best;
 }
 

@@ -258,12 +258,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         lat = tile.lat;
         x0 = tile.x0;
         y0 = tile.y0;
-        const LatticeRec& Rl = args.recs[lat];
-        nx = Rl.nx;
-        ny = Rl.ny;
-        sx = Rl.slow_x;
-        sy = Rl.slow_y;
-        soff = Rl.state_offset;
+        nx = tile.nx;
+        ny = tile.ny;
+        sx = tile.slow & 1;
+        sy = tile.slow >> 1;
+        soff = tile.soff;
     }
     const LatticeRec& R = args.recs[lat];
     const int N = nx * ny;
@@ -334,7 +333,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         }
     }
     // Blown-up lattices are frozen.  The flag can be raised by other blocks while
-    // this one runs, so one thread reads it and the whole block follows.
+    // this one runs, so one thread reads it and the whole block follows.  (The
+    // runtime leaves the tiles of lattices it has reported blown up out of its
+    // plan, so this mostly catches lattices that blew up since.)
     __shared__ unsigned s_skip;
     if (tid == 0) s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
     // a mirror image beyond a plate carries the reflected momentum (j_y negated)

@@ -44,9 +44,14 @@ struct LatticeRec {
     double c0;                          // improved scheme: p_m = (c0 + mu)/3 (the paper: 1)
 };
 
-// One unit of work: an output tile (2D) or an output column chunk (3D).
+// One unit of work: an output tile (2D) or an output column chunk (3D).  It also
+// carries its lattice's extents, wrap flags and state offset, so that a batch's
+// tile can issue its pulls as soon as this record has arrived.
 struct Tile {
-    int lat, x0, y0, z0, zn, pad0, pad1, pad2;
+    int lat, x0, y0, z0, zn;
+    int nx, ny;
+    int slow;                 // bit 0: slow wrap in x, bit 1: in y (lattice narrower than a tile + 8)
+    long long soff;           // the lattice's state offset in nodes
 };
 
 // Order of the D2Q9 tiles of one lattice: bands of `band` tile columns, taken

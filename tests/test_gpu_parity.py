@@ -207,6 +207,51 @@ def test_blowup_is_flagged_and_isolated():
     solo.close()
 
 
+def test_reported_blowup_leaves_the_plan_until_reinit():
+    """Once lbm_diagnostics reports a lattice blown up, the runtime drops its tiles:
+    its populations stay as they were, a repeated diagnostics call gives the same
+    values, the other lattice keeps matching its solo run through re-tiling, and
+    re-initialising brings the lattice back."""
+    p_bad = runtime.params("D2Q9", 32, 32, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    p_ok = runtime.params("D2Q9", 48, 40, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
+    bad = np.full((32, 32), 2.0)
+    bad[10, 10] = 1.2 / (2.0 / 21.0)
+    good = _droplet((40, 48), "vdW", 0.8, 9.0)
+    print("case batch with a lattice dropped from the plan", flush=True)
+    sim = runtime.LBM([p_bad, p_ok])
+    sim.init(np.concatenate([bad.ravel(), good.ravel()]))
+    sim.step(10)
+    d1 = sim.diagnostics()
+    assert d1[0]["status"] != 0 and d1[1]["status"] == 0
+    assert sim.diagnostics() == d1
+    off = sim.offsets()[1]
+    frozen = sim.get_f()[:, :off].cpu()
+    sim.step(7)
+    sim.set_tile_shape((runtime._lib.lib().lbm_get_tile_shape(sim.h) + 1) % sim.num_tile_shapes())
+    sim.step(8)
+    solo = runtime.LBM(p_ok)
+    solo.init(good)
+    solo.step(25)
+    # bit-identical, NaNs of the blown-up state included
+    torch.testing.assert_close(sim.get_f()[:, :off].cpu(), frozen, rtol=0, atol=0, equal_nan=True)
+    assert torch.equal(sim.get_f()[:, off:].cpu(), solo.get_f().cpu())
+    d2 = sim.diagnostics()
+    assert d2[0]["status"] != 0 and d2[1]["status"] == 0 and d2[1]["step"] == 24
+    assert d2[1]["mass"] == pytest.approx(float(good.sum()), rel=1e-13)
+    # re-initialised with a sound state, both lattices run again
+    other = _droplet((32, 32), "vdW", 0.8, 7.0, seed=3)
+    sim.init(np.concatenate([other.ravel(), good.ravel()]))
+    sim.step(5)
+    d3 = sim.diagnostics()
+    assert d3[0]["status"] == 0 and d3[1]["status"] == 0
+    alone = runtime.LBM(p_bad)
+    alone.init(other)
+    alone.step(5)
+    assert torch.equal(sim.get_f()[:, :off].cpu()[:, :32 * 32], alone.get_f().cpu())
+    for x in (sim, solo, alone):
+        x.close()
+
+
 def test_state_round_trips_and_zero_steps():
     p = runtime.params("D2Q9", 30, 20, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
     rho0 = _droplet((20, 30), "vdW", 0.8, 6.0)
