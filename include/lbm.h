@@ -297,9 +297,11 @@ int lbm_set_use_graphs(lbm_ctx* h, int on);
  * afterwards); returns the chosen index. */
 int lbm_autotune(lbm_ctx* h, int steps, void* scratch_state);
 
-/* Measurement helper: copy `bytes` from src to dst on the handle-less stream
- * `hip_stream` with a plain vectorised copy kernel (used to calibrate traffic
- * counters against a kernel of known size). */
+/* Measurement helper: copy `bytes` from src to dst (device, 16-byte aligned,
+ * not overlapping) on the stream `hip_stream` with a plain copy kernel, one
+ * 16-byte vector per thread; the reference of known size for the traffic
+ * counters and the streaming ceiling.  LBM_ERR_ARG for null or misaligned
+ * pointers. */
 int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 const char* lbm_error_string(int code);

@@ -908,6 +908,7 @@ int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double*
 
 int lbm_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream) {
     if (!dst || !src) return fail(LBM_ERR_ARG, "null argument");
+    if (((uintptr_t)dst | (uintptr_t)src) & 15) return fail(LBM_ERR_ARG, "buffers must be 16-byte aligned");
     HIP_TRY(launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream)));
     return LBM_OK;
 }
