@@ -1,6 +1,6 @@
 """Throughput benchmark of the fused free-energy LB step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-secondary] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-secondary] [--no-cpu-baseline] [--no-accuracy]
 
 Primary workload (the metric's configuration): D2Q9 512 x 512 periodic lattice,
 Carnahan-Starling droplet of radius 80 at T/Tc = 0.8, kappa = 0.01, tau = 0.8,
@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graphs", action="store_true", help="one kernel launch per step (for counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape (no autotuning)")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the 5e4-step float32/float64 accuracy runs")
     ap.add_argument("--tile", type=int, default=-1, help="force this tile-shape index (no autotuning)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run the plain copy kernel on this many MiB, 5 times (traffic-counter calibration)")
@@ -420,7 +421,7 @@ def main():
             print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s)",
                   file=sys.stderr, flush=True)
     acc = None
-    if not args.no_secondary:
+    if not args.no_secondary and not args.no_accuracy and not args.no_graphs:
         acc = accuracy(torch, runtime, inputs)
         print(f"[bench] accuracy after {acc['steps']} steps: fp32 vs fp64 rho_l {acc['fp32_vs_fp64_rel']['rho_l']:.1e}, "
               f"rho_g {acc['fp32_vs_fp64_rel']['rho_g']:.1e}; max_u fp64 {acc['fp64']['max_u']:.1e}, "
