@@ -259,10 +259,13 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
 int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar,
                        double* lam_out, void* ws, double* grad);
 /* lbm_adjoint_segment: one checkpoint segment of a checkpointed backward pass.
- * Restores `checkpoint` (raw state of time level t0, lbm_get_state layout) into
- * the handle, recomputes the m >= 1 states of time levels t0 .. t0+m-1 into
- * `states` (device, m * lbm_state_bytes, caller-owned, overwritten), then runs
- * lbm_adjoint_step from t0+m-1 down to t0.  On entry lam holds dL/df(t0+m), on
+ * Copies `checkpoint` (raw state of time level t0, lbm_get_state layout) into
+ * the first of the m >= 1 slots of `states` (device, m * lbm_state_bytes,
+ * caller-owned, overwritten), recomputes the states of time levels t0+1 ..
+ * t0+m-1 into the next slots, then runs lbm_adjoint_step from t0+m-1 down to
+ * t0.  checkpoint, states, lam and lam2 must be 16-byte aligned.  With graphs
+ * on (lbm_set_use_graphs) the segment's launches are captured once per segment
+ * length and buffer set and replayed.  On entry lam holds dL/df(t0+m), on
  * exit dL/df(t0) (layout of lbm_get_f); lam2 is device scratch of the same size
  * (must not alias lam); grad is incremented as by lbm_adjoint_step.  The handle is
  * left at time level t0 + m with no diagnostics.  Same support as the calls above. */

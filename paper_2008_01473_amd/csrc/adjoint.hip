@@ -368,7 +368,9 @@ __global__ void adj_init_local(AdjArgs a) {
 
 // Sum the block partials and add them to the two accumulators: one wave, lane l
 // summing blocks l, l + 64, ... in order, then a fixed butterfly across the lanes,
-// so that every run adds in the same order.
+// so that every run adds in the same order.  (A last-block-done reduction inside
+// adj_final was measured slower: the device-scope fence of every block costs more
+// than this launch.)
 __global__ void adj_reduce(const double* partial, int nblocks, double* grad) {
     const int lane = threadIdx.x;
     double k = 0, t = 0;

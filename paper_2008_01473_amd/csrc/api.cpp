@@ -11,6 +11,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -120,9 +121,15 @@ struct lbm_ctx {
     DiagOut* d_diag() const { return reinterpret_cast<DiagOut*>(ws + off_diag); }
     int zchunk_for(int s) const;
     std::vector<Tile> plan(int s, std::vector<LatticeRec>& rr) const;
+    // Adjoint segments (lbm_adjoint_segment) replayed from graphs, keyed by the
+    // segment length, the buffer parity and the caller's buffers.
+    using SegKey = std::tuple<int, int, const void*, const void*, const void*, const void*, const void*>;
+    std::map<SegKey, hipGraphExec_t> seg_graphs;
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);   // teardown: nothing to report
         graphs.clear();
+        for (auto& kv : seg_graphs) (void)hipGraphExecDestroy(kv.second);
+        seg_graphs.clear();
     }
 };
 
@@ -850,6 +857,71 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
     return LBM_OK;
 }
 
+namespace {
+
+// The work of one adjoint segment after its checkpoint has been restored: the
+// recompute of states t0 .. t0 + m - 1 (each kept in `states`) and the adjoint
+// steps back through them.  Leaves h->cur as the recompute leaves it.
+int enqueue_segment(lbm_ctx* h, int m, void* states, double* lam, double* lam2, void* ws, double* grad,
+                    hipStream_t s) {
+    // slot 0 holds the checkpoint; each recompute step writes the next slot, the
+    // last one the handle's current buffer (the handle ends at t0 + m)
+    char* st = reinterpret_cast<char*>(states);
+    for (int k = 0; k < m; ++k) {
+        StepArgs a = base_args(h);
+        a.src = st + (size_t)k * h->state_bytes;
+        a.dst = k + 1 < m ? static_cast<void*>(st + (size_t)(k + 1) * h->state_bytes) : h->buf[h->cur];
+        HIP_TRY(launch_step(h, a, kStep, s));
+    }
+    double* in = lam;
+    double* out = lam2;
+    for (int k = m - 1; k >= 0; --k) {
+        HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved,
+                               st + (size_t)k * h->state_bytes, in, out, nullptr, nullptr, nullptr, nullptr,
+                               reinterpret_cast<double*>(ws), grad, s));
+        std::swap(in, out);
+    }
+    if (in != lam) HIP_TRY(launch_copy(lam, in, (size_t)9 * h->recs[0].nnodes * sizeof(double), s));
+    return LBM_OK;
+}
+
+// A segment's launches captured once and replayed (keyed by the buffers, so a
+// caller that keeps its buffers replays one graph per segment).
+int segment_graph(lbm_ctx* h, int m, void* states, double* lam, double* lam2, void* ws, double* grad,
+                  hipGraphExec_t* out) {
+    const lbm_ctx::SegKey key{m, h->cur, states, lam, lam2, ws, grad};
+    auto it = h->seg_graphs.find(key);
+    if (it != h->seg_graphs.end()) {
+        *out = it->second;
+        return LBM_OK;
+    }
+    if (h->seg_graphs.size() >= 8) {           // callers with fresh buffers every time: keep a few
+        for (auto& kv : h->seg_graphs) (void)hipGraphExecDestroy(kv.second);
+        h->seg_graphs.clear();
+    }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const int saved = h->cur;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_segment(h, m, states, lam, lam2, ws, grad, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    h->cur = saved;
+    if (rc != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->seg_graphs[key] = ex;
+    *out = ex;
+    return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m, void* states, double* lam,
                         double* lam2, void* ws, double* grad) {
     int rc = adjoint_check(h);
@@ -857,30 +929,24 @@ int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m,
     if (!checkpoint || !states || !lam || !lam2 || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
     if (m < 1) return fail(LBM_ERR_ARG, "m must be >= 1");
     if (lam == lam2) return fail(LBM_ERR_ARG, "lam and lam2 must not alias");
-    rc = lbm_set_state(h, checkpoint, t0);
+    if (((uintptr_t)states | (uintptr_t)lam | (uintptr_t)lam2 | (uintptr_t)checkpoint) & 15)
+        return fail(LBM_ERR_ARG, "checkpoint, states, lam and lam2 must be 16-byte aligned");
+    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
+    rc = reset_status(h);
     if (rc != LBM_OK) return rc;
-    char* st = reinterpret_cast<char*>(states);
-    // recompute the segment's states t0 .. t0 + m - 1 (no diagnostics needed)
-    for (int k = 0; k < m; ++k) {
-        HIP_TRY(hipMemcpyAsync(st + (size_t)k * h->state_bytes, h->buf[h->cur], h->state_bytes,
-                               hipMemcpyDeviceToDevice, h->stream));
-        rc = enqueue_steps(h, 1, h->stream, kStep);
+    HIP_TRY(launch_copy(states, checkpoint, h->state_bytes, h->stream));
+    if (h->use_graphs) {
+        hipGraphExec_t ex = nullptr;
+        rc = segment_graph(h, m, states, lam, lam2, ws, grad, &ex);
+        if (rc != LBM_OK) return rc;
+        HIP_TRY(hipGraphLaunch(ex, h->stream));
+    } else {
+        rc = enqueue_segment(h, m, states, lam, lam2, ws, grad, h->stream);
         if (rc != LBM_OK) return rc;
     }
     h->t = t0 + m;
     h->t_diag = -1;
-    // back through them: dL/df(t) from dL/df(t + 1)
-    double* in = lam;
-    double* out = lam2;
-    for (int k = m - 1; k >= 0; --k) {
-        HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved,
-                               st + (size_t)k * h->state_bytes, in, out, nullptr, nullptr, nullptr, nullptr,
-                               reinterpret_cast<double*>(ws), grad, h->stream));
-        std::swap(in, out);
-    }
-    if (in != lam)
-        HIP_TRY(hipMemcpyAsync(lam, in, (size_t)9 * h->recs[0].nnodes * sizeof(double), hipMemcpyDeviceToDevice,
-                               h->stream));
+    h->inited = true;
     return LBM_OK;
 }
 
