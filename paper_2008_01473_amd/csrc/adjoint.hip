@@ -28,6 +28,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lbm_device.hpp"
 #include "lbm_shared.hpp"
 
@@ -130,24 +132,7 @@ __device__ __forceinline__ double state_f(const AdjArgs& a, int q, int x, int y)
 }
 
 // ---- forward fields -----------------------------------------------------------
-template <typename S>
-__global__ void fwd_moments(AdjArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const int x = i % a.nx, y = i / a.nx;
-    double r = 0, jx = 0, jy = 0;
-    for (int q = 0; q < 9; ++q) {
-        const double f = state_f<S>(a, q, x, y);
-        r += f;
-        jx += EX[q] * f;
-        jy += EY[q] * f;
-    }
-    F(a, RHO)[i] = r;
-    F(a, JX)[i] = jx;
-    F(a, JY)[i] = jy;
-}
-
-// mu and the EOS derivatives; the density comes from RHO (steps) or rho0 (init).
+// mu and the EOS derivatives of the initial density (init mode).
 __global__ void fwd_mu(AdjArgs a, int from_rho0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
@@ -162,54 +147,17 @@ __global__ void fwd_mu(AdjArgs a, int from_rho0) {
     F(a, MUT)[i] = dt;
 }
 
-__global__ void fwd_force(AdjArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const Nbr n = nbr(i, a.nx, a.ny);
-    const double r = F(a, RHO)[i];
-    const double gx = ddx(F(a, MU), n, a.nx), gy = ddy(F(a, MU), n, a.nx);
-    double Fx, Fy;
-    if (a.improved) {
-        Fx = (1.0 / 3.0 - r) * gx;
-        Fy = (1.0 / 3.0 - r) * gy;
-    } else {
-        Fx = ddx(F(a, RHO), n, a.nx) / 3.0 - r * gx;
-        Fy = ddy(F(a, RHO), n, a.nx) / 3.0 - r * gy;
-    }
-    F(a, GX)[i] = gx;
-    F(a, GY)[i] = gy;
-    F(a, FX)[i] = Fx;
-    F(a, FY)[i] = Fy;
-    F(a, UX)[i] = (F(a, JX)[i] + 0.5 * Fx) / r;
-    F(a, UY)[i] = (F(a, JY)[i] + 0.5 * Fy) / r;
-}
-
 // ---- adjoint ---------------------------------------------------------------------
-// A1: local adjoint of the collision (or the given field cotangents).
-__global__ void adj_local(AdjArgs a, int fields_mode) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    if (fields_mode) {
-        F(a, RB)[i] = a.rho_bar ? a.rho_bar[i] : 0.0;
-        F(a, UXB)[i] = a.u_bar ? a.u_bar[i] : 0.0;
-        F(a, UYB)[i] = a.u_bar ? a.u_bar[a.N + i] : 0.0;
-        F(a, PB)[i] = 0.0;
-        F(a, FXB)[i] = 0.0;
-        F(a, FYB)[i] = 0.0;
-        F(a, DXB)[i] = 0.0;
-        F(a, DYB)[i] = 0.0;
-        return;
-    }
-    const Nbr n = nbr(i, a.nx, a.ny);
+// A1: local adjoint of the collision at node i; lam[q] = lam_in(x + e_q).
+__device__ __forceinline__ void collision_vjp(const AdjArgs& a, int i, const double (&lam)[9], double r, double ux,
+                                              double uy, double Fx, double Fy, double mu) {
     const double w = a.rec.omega, w2 = 1.0 - 0.5 * w;
-    const double r = F(a, RHO)[i], ux = F(a, UX)[i], uy = F(a, UY)[i];
-    const double Fx = F(a, FX)[i], Fy = F(a, FY)[i];
-    const double pm = a.improved ? (a.rec.c0 + F(a, MU)[i]) / 3.0 : r / 3.0;
+    const double pm = a.improved ? (a.rec.c0 + mu) / 3.0 : r / 3.0;
     const double php = pm - r / 3.0;
     const double usq = ux * ux + uy * uy;
     double rb = 0, uxb = 0, uyb = 0, pb = 0, fxb = 0, fyb = 0, cxxb = 0, cyyb = 0;
     for (int q = 0; q < 9; ++q) {
-        const double ab = a.lam_in[(size_t)q * a.N + at(n, EX[q], EY[q], a.nx)];   // lam(x + e_q)
+        const double ab = lam[q];
         const double ex = EX[q], ey = EY[q];
         const double eu = ex * ux + ey * uy, eF = ex * Fx + ey * Fy;
         const double fe = w * ab, gb = w2 * ab;
@@ -253,60 +201,245 @@ __global__ void adj_local(AdjArgs a, int fields_mode) {
     F(a, DYB)[i] = 3.0 * cyyb;
 }
 
-// A2: psi_bar = -d(d_bar); phi, p_m, u and F adjoints at the node.
-__global__ void adj_velocity(AdjArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const Nbr n = nbr(i, a.nx, a.ny);
-    const double r = F(a, RHO)[i], ux = F(a, UX)[i], uy = F(a, UY)[i];
-    double rb = F(a, RB)[i], uxb = F(a, UXB)[i], uyb = F(a, UYB)[i], pb = F(a, PB)[i];
-    double fxb = F(a, FXB)[i], fyb = F(a, FYB)[i];
-    double mub = 0.0;
-    if (a.improved) {
-        const double psixb = -ddx(F(a, DXB), n, a.nx);
-        const double psiyb = -ddy(F(a, DYB), n, a.nx);
-        const double pm = (a.rec.c0 + F(a, MU)[i]) / 3.0;
-        const double phi = r / 3.0 - pm;
-        const double phib = psixb * ux + psiyb * uy;
-        uxb += phi * psixb;
-        uyb += phi * psiyb;
-        rb += phib / 3.0;
-        pb -= phib;
-        mub = pb / 3.0;
-    } else {
-        rb += pb / 3.0;
+// A0 + A1 fused on a tile of TX x TY nodes: rho, j on the tile + 2 rings and mu on
+// the tile + 1 ring in LDS, then at each node of the tile g = grad mu, F, u and the
+// local adjoint of the collision (the same formulas, in the same order, as
+// fwd_moments, fwd_mu, fwd_force and adj_local, which it replaces in the step and
+// fields modes).
+constexpr int TX = 32, TY = 8;
+constexpr int RW = TX + 4, RH = TY + 4;      // rho, j: tile + 2
+constexpr int MW = TX + 2, MH = TY + 2;      // mu: tile + 1
+
+__device__ __forceinline__ int wrapn(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+template <int W>
+__device__ __forceinline__ double lds_ddx(const double* p, int c) {
+    return (4.0 * (p[c + 1] - p[c - 1]) + (p[c + W + 1] - p[c + W - 1]) + (p[c - W + 1] - p[c - W - 1])) / 12.0;
+}
+template <int W>
+__device__ __forceinline__ double lds_ddy(const double* p, int c) {
+    return (4.0 * (p[c + W] - p[c - W]) + (p[c + W + 1] + p[c + W - 1]) - (p[c - W - 1] + p[c - W + 1])) / 12.0;
+}
+template <int W>
+__device__ __forceinline__ double lds_lap(const double* p, int c) {
+    return (4.0 * (p[c + 1] + p[c - 1] + p[c + W] + p[c - W]) + (p[c + W + 1] + p[c + W - 1] + p[c - W - 1] +
+                                                                   p[c - W + 1]) -
+            20.0 * p[c]) /
+           6.0;
+}
+
+template <typename S>
+__global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) {
+    __shared__ double s_rho[RH * RW], s_jx[RH * RW], s_jy[RH * RW];
+    __shared__ double s_mu[MH * MW];
+    const int nx = a.nx, ny = a.ny;
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+    const int i = own ? gy * nx + gx : 0;
+    const Nbr n = nbr(i, nx, ny);
+    // the cotangents gathered by the collision adjoint, lam(x + e_q), are loaded
+    // first so that their latency overlaps the stages below
+    double lam[9];
+    if (own && !fields_mode) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) lam[q] = a.lam_in[(size_t)q * a.N + at(n, EX[q], EY[q], nx)];
     }
-    const double ir = 1.0 / r;
-    F(a, JXB)[i] = uxb * ir;
-    F(a, JYB)[i] = uyb * ir;
-    fxb += 0.5 * uxb * ir;
-    fyb += 0.5 * uyb * ir;
-    rb -= (uxb * ux + uyb * uy) * ir;
-    rb -= fxb * F(a, GX)[i] + fyb * F(a, GY)[i];
-    const double gfac = a.improved ? (1.0 / 3.0 - r) : -r;
-    F(a, GXB)[i] = gfac * fxb;
-    F(a, GYB)[i] = gfac * fyb;
-    F(a, FXB)[i] = fxb;
-    F(a, FYB)[i] = fyb;
-    F(a, RB)[i] = rb;
-    F(a, MUB)[i] = mub;
+    // rho and j on the tile + 2 rings (periodic): both of a thread's nodes' pulls
+    // are issued before either is summed
+    constexpr int NT = TX * TY, NR = (RH * RW + NT - 1) / NT;
+    double fr[NR][9];
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+        const int k = tid + h * NT;
+        if (k < RH * RW) {
+            const int x = wrapn(x0 - 2 + k % RW, nx), y = wrapn(y0 - 2 + k / RW, ny);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fr[h][q] = state_f<S>(a, q, x, y);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+        const int k = tid + h * NT;
+        if (k < RH * RW) {
+            double r = 0, jx = 0, jy = 0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                r += fr[h][q];
+                jx += EX[q] * fr[h][q];
+                jy += EY[q] * fr[h][q];
+            }
+            s_rho[k] = r;
+            s_jx[k] = jx;
+            s_jy[k] = jy;
+        }
+    }
+    __syncthreads();
+    // mu on the tile + 1 ring; L, dmu/drho and dmu/d(T/Tc) of the tile's nodes
+    for (int k = tid; k < MH * MW; k += TX * TY) {
+        const int mx = k % MW, my = k / MW;
+        const int c = (my + 1) * RW + mx + 1;
+        double mu, dr, dt;
+        eos_terms(a.rec, a.dRT, s_rho[c], mu, dr, dt);
+        const double L = lds_lap<RW>(s_rho, c);
+        s_mu[k] = mu - a.rec.kappa * L;
+        const int hx = x0 - 1 + mx, hy = y0 - 1 + my;
+        if (mx >= 1 && mx <= TX && my >= 1 && my <= TY && hx < nx && hy < ny) {
+            const int ih = hy * nx + hx;
+            F(a, LR)[ih] = L;
+            F(a, MUR)[ih] = dr;
+            F(a, MUT)[ih] = dt;
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+    const int cr = (ly + 2) * RW + lx + 2, cm = (ly + 1) * MW + lx + 1;
+    const double r = s_rho[cr];
+    const double gxv = lds_ddx<MW>(s_mu, cm), gyv = lds_ddy<MW>(s_mu, cm);
+    double Fx, Fy;
+    if (a.improved) {
+        Fx = (1.0 / 3.0 - r) * gxv;
+        Fy = (1.0 / 3.0 - r) * gyv;
+    } else {
+        Fx = lds_ddx<RW>(s_rho, cr) / 3.0 - r * gxv;
+        Fy = lds_ddy<RW>(s_rho, cr) / 3.0 - r * gyv;
+    }
+    const double ux = (s_jx[cr] + 0.5 * Fx) / r;
+    const double uy = (s_jy[cr] + 0.5 * Fy) / r;
+    const double muv = s_mu[cm];
+    F(a, RHO)[i] = r;
+    F(a, MU)[i] = muv;
+    F(a, GX)[i] = gxv;
+    F(a, GY)[i] = gyv;
+    F(a, UX)[i] = ux;
+    F(a, UY)[i] = uy;
+    if (fields_mode) {
+        F(a, RB)[i] = a.rho_bar ? a.rho_bar[i] : 0.0;
+        F(a, UXB)[i] = a.u_bar ? a.u_bar[i] : 0.0;
+        F(a, UYB)[i] = a.u_bar ? a.u_bar[a.N + i] : 0.0;
+        F(a, PB)[i] = 0.0;
+        F(a, FXB)[i] = 0.0;
+        F(a, FYB)[i] = 0.0;
+        F(a, DXB)[i] = 0.0;
+        F(a, DYB)[i] = 0.0;
+        return;
+    }
+    collision_vjp(a, i, lam, r, ux, uy, Fx, Fy, muv);
 }
 
-// A3: mu_bar -= div(g_bar); standard force: rho_bar -= div(F_bar)/3.
-__global__ void adj_mu(AdjArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    const Nbr n = nbr(i, a.nx, a.ny);
-    // written to separate slots: PB holds mu_bar, DXB the updated rho_bar
-    const double mub = F(a, MUB)[i] - (ddx(F(a, GXB), n, a.nx) + ddy(F(a, GYB), n, a.nx));
-    double rb = F(a, RB)[i];
-    if (!a.improved) rb -= (ddx(F(a, FXB), n, a.nx) + ddy(F(a, FYB), n, a.nx)) / 3.0;
-    F(a, PB)[i] = mub;
-    F(a, DXB)[i] = rb;
+// A2 - A4 fused on a tile (step and fields modes): on the tile + 2 rings the
+// psi, phi, p_m, u and F adjoints (psi_bar = -d(d_bar)), on the tile + 1 ring
+// mu_bar -= div(g_bar) (standard force: rho_bar -= div(F_bar)/3), and on the tile
+// rho_bar through mu, the parameter partials and dL/df(t).  The same formulas,
+// in the same order, as the per-node kernels they replaced.
+__global__ __launch_bounds__(TX* TY) void adj_back(AdjArgs a, int mode) {
+    constexpr int NT = TX * TY, VN = RH * RW, MN = MH * MW;
+    __shared__ double s_gxb[VN], s_gyb[VN], s_fxb[VN], s_fyb[VN], s_rb[VN], s_mub[VN], s_jxb[VN], s_jyb[VN];
+    __shared__ double s_mub2[MN], s_rb2[MN];
+    __shared__ double sk[NT], st[NT];
+    const int nx = a.nx, ny = a.ny;
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+    const int i = own ? gy * nx + gx : 0;
+    const Nbr n = nbr(i, nx, ny);
+    double lam[9];
+    if (own && mode == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) lam[q] = a.lam_in[(size_t)q * a.N + at(n, EX[q], EY[q], nx)];
+    }
+    // psi, phi, p_m, u and F adjoints on the tile + 2 rings
+    for (int k = tid; k < VN; k += NT) {
+        const int x = wrapn(x0 - 2 + k % RW, nx), y = wrapn(y0 - 2 + k / RW, ny);
+        const int j = y * nx + x;
+        const Nbr m = nbr(j, nx, ny);
+        const double r = F(a, RHO)[j], ux = F(a, UX)[j], uy = F(a, UY)[j];
+        double rb = F(a, RB)[j], uxb = F(a, UXB)[j], uyb = F(a, UYB)[j], pb = F(a, PB)[j];
+        double fxb = F(a, FXB)[j], fyb = F(a, FYB)[j];
+        double mub = 0.0;
+        if (a.improved) {
+            const double psixb = -ddx(F(a, DXB), m, nx);
+            const double psiyb = -ddy(F(a, DYB), m, nx);
+            const double pm = (a.rec.c0 + F(a, MU)[j]) / 3.0;
+            const double phi = r / 3.0 - pm;
+            const double phib = psixb * ux + psiyb * uy;
+            uxb += phi * psixb;
+            uyb += phi * psiyb;
+            rb += phib / 3.0;
+            pb -= phib;
+            mub = pb / 3.0;
+        } else {
+            rb += pb / 3.0;
+        }
+        const double ir = 1.0 / r;
+        s_jxb[k] = uxb * ir;
+        s_jyb[k] = uyb * ir;
+        fxb += 0.5 * uxb * ir;
+        fyb += 0.5 * uyb * ir;
+        rb -= (uxb * ux + uyb * uy) * ir;
+        rb -= fxb * F(a, GX)[j] + fyb * F(a, GY)[j];
+        const double gfac = a.improved ? (1.0 / 3.0 - r) : -r;
+        s_gxb[k] = gfac * fxb;
+        s_gyb[k] = gfac * fyb;
+        s_fxb[k] = fxb;
+        s_fyb[k] = fyb;
+        s_rb[k] = rb;
+        s_mub[k] = mub;
+    }
+    __syncthreads();
+    // mu_bar -= div(g_bar) on the tile + 1 ring
+    for (int k = tid; k < MN; k += NT) {
+        const int c = (k / MW + 1) * RW + k % MW + 1;
+        s_mub2[k] = s_mub[c] - (lds_ddx<RW>(s_gxb, c) + lds_ddy<RW>(s_gyb, c));
+        double rb = s_rb[c];
+        if (!a.improved) rb -= (lds_ddx<RW>(s_fxb, c) + lds_ddy<RW>(s_fyb, c)) / 3.0;
+        s_rb2[k] = rb;
+    }
+    __syncthreads();
+    // rho_bar through mu, parameter partials, dL/df(t)
+    double kb = 0.0, tb = 0.0;
+    if (own) {
+        const int cm = (ly + 1) * MW + lx + 1, cr = (ly + 2) * RW + lx + 2;
+        const double mub = s_mub2[cm];
+        double rb = s_rb2[cm];
+        rb += F(a, MUR)[i] * mub - a.rec.kappa * lds_lap<MW>(s_mub2, cm);
+        kb = -mub * F(a, LR)[i];
+        tb = mub * F(a, MUT)[i];
+        const double jxb = s_jxb[cr], jyb = s_jyb[cr];
+        const double w1 = 1.0 - a.rec.omega;
+        for (int q = 0; q < 9; ++q) {
+            double v = rb + EX[q] * jxb + EY[q] * jyb;
+            if (mode == 0) v += w1 * lam[q];
+            a.lam_out[(size_t)q * a.N + i] = v;
+        }
+    }
+    // tile partial sums of the parameter gradients, in a fixed order
+    sk[tid] = kb;
+    st[tid] = tb;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            sk[tid] += sk[tid + w];
+            st[tid] += st[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.partial[2 * blockIdx.x] = sk[0];
+        a.partial[2 * blockIdx.x + 1] = st[0];
+    }
 }
 
-// A4: rho_bar through mu; parameter gradients; dL/df(t) (or dL/drho0 in init mode).
-// mode 0: step, 1: fields, 2: init (reads PB = mu_bar, RB = rho_bar from adj_init_local).
+// Init mode, after adj_init_local: rho_bar through mu (PB = mu_bar, RB = rho_bar),
+// the parameter partials and dL/drho0 (mode 2; modes 0 and 1 are adj_back's).
 __global__ __launch_bounds__(256) void adj_final(AdjArgs a, int mode) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double kb = 0.0, tb = 0.0;
@@ -388,8 +521,11 @@ __global__ void adj_reduce(const double* partial, int nblocks, double* grad) {
 
 }  // namespace adj
 
-size_t adjoint_workspace_doubles(long long N) {
-    const long long blocks = (N + 255) / 256;
+// Fields and two partial sums per block: 256-node blocks (init mode) or tiles.
+size_t adjoint_workspace_doubles(int nx, int ny) {
+    const long long N = (long long)nx * ny;
+    const long long tiles = (long long)((nx + adj::TX - 1) / adj::TX) * ((ny + adj::TY - 1) / adj::TY);
+    const long long blocks = std::max<long long>((N + 255) / 256, tiles);
     return (size_t)adj::NFIELDS * (size_t)N + 2 * (size_t)blocks;
 }
 
@@ -422,17 +558,13 @@ hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int preci
         hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, G, grad);
         return hipGetLastError();
     }
+    const int tiles = ((a.nx + adj::TX - 1) / adj::TX) * ((a.ny + adj::TY - 1) / adj::TY);
     if (precision == 0)
-        hipLaunchKernelGGL(adj::fwd_moments<double>, dim3(G), dim3(B), 0, s, a);
+        hipLaunchKernelGGL(adj::adj_front<double>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
     else
-        hipLaunchKernelGGL(adj::fwd_moments<float>, dim3(G), dim3(B), 0, s, a);
-    hipLaunchKernelGGL(adj::fwd_mu, dim3(G), dim3(B), 0, s, a, 0);
-    hipLaunchKernelGGL(adj::fwd_force, dim3(G), dim3(B), 0, s, a);
-    hipLaunchKernelGGL(adj::adj_local, dim3(G), dim3(B), 0, s, a, kind == 1 ? 1 : 0);
-    hipLaunchKernelGGL(adj::adj_velocity, dim3(G), dim3(B), 0, s, a);
-    hipLaunchKernelGGL(adj::adj_mu, dim3(G), dim3(B), 0, s, a);
-    hipLaunchKernelGGL(adj::adj_final, dim3(G), dim3(B), 0, s, a, kind == 1 ? 1 : 0);
-    hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, G, grad);
+        hipLaunchKernelGGL(adj::adj_front<float>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
+    hipLaunchKernelGGL(adj::adj_back, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
+    hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, tiles, grad);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ hipError_t launch_finalize(const DiagPartial* partial, const LatticeRec* recs, c
                            DiagOut* out, int nlat, hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
-size_t adjoint_workspace_doubles(long long N);
+size_t adjoint_workspace_doubles(int nx, int ny);
 hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int precision, int improved, const void* state,
                           const double* lam_in, double* lam_out, const double* rho_bar, const double* u_bar,
                           const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s);
@@ -842,7 +842,7 @@ double adjoint_dRT(const lbm_ctx* h) {
 
 size_t lbm_adjoint_workspace_bytes(const lbm_ctx* h) {
     if (!h || h->lattice != LBM_D2Q9 || h->recs.size() != 1 || h->recs[0].mrt || h->recs[0].walls) return 0;
-    return align256(adjoint_workspace_doubles(h->recs[0].nnodes) * sizeof(double));
+    return align256(adjoint_workspace_doubles(h->recs[0].nx, h->recs[0].ny) * sizeof(double));
 }
 
 int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out, void* ws,

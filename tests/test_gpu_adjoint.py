@@ -35,9 +35,12 @@ def _case(scheme, n=(20, 24), T=0.8, kappa=0.02, tau=0.8, seed=0, c0=1.0):
     return p, rho0
 
 
-@pytest.mark.parametrize("scheme,c0", [("improved", 1.0), ("standard", 1.0), ("improved", 0.7)])
-def test_adjoint_step_matches_oracle_autograd(scheme, c0):
-    p, rho0 = _case(scheme, c0=c0)
+@pytest.mark.parametrize("scheme,c0,n", [("improved", 1.0, (20, 24)), ("standard", 1.0, (20, 24)),
+                                         ("improved", 0.7, (20, 24)),
+                                         # several 32 x 8 tiles, ragged in both directions
+                                         ("improved", 1.0, (19, 70)), ("standard", 1.0, (19, 70))])
+def test_adjoint_step_matches_oracle_autograd(scheme, c0, n):
+    p, rho0 = _case(scheme, n=n, c0=c0)
     shape = shape_of(p)
     kap = torch.tensor(0.02, dtype=torch.float64, requires_grad=True)
     tt = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
@@ -61,7 +64,7 @@ def test_adjoint_step_matches_oracle_autograd(scheme, c0):
                                   roll.ws.data_ptr(), grad.data_ptr()))
     torch.cuda.synchronize()
     e = rel_err(lam_out.view(9, *shape), gf)
-    print(f"adjoint step {scheme}: rel err lambda {e:.2e}, kappa {float(grad[0]):.6e} vs {float(gk):.6e}, "
+    print(f"adjoint step {scheme} {n}: rel err lambda {e:.2e}, kappa {float(grad[0]):.6e} vs {float(gk):.6e}, "
           f"T {float(grad[1]):.6e} vs {float(gt):.6e}", flush=True)
     assert e < 1e-12
     assert float(grad[0]) == pytest.approx(float(gk), rel=1e-10, abs=1e-14)
