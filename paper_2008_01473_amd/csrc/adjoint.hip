@@ -58,6 +58,8 @@ struct AdjArgs {
     double* grad_rho0;      // output of the init mode
     double* ws;             // NFIELDS * N doubles
     double* partial;        // 2 doubles per block
+    double* grad;           // [kappa_bar, (T/Tc)_bar], incremented
+    int pending;            // partials of the previous adjoint step wait in `partial` (blocks)
     LatticeRec rec;
     double dRT;             // d(R T) / d(T/Tc) = R T_c
     int N, nx, ny, improved, precision;
@@ -238,6 +240,22 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
     const int tid = threadIdx.x;
+    // Within a segment the previous adjoint step's parameter partials are added
+    // here (the sum adj_reduce would take, in the same order) before adj_back
+    // overwrites them, which saves a launch per step.
+    if (a.pending && blockIdx.x == 0 && tid < 64) {
+        double k = 0, t = 0;
+        for (int b = tid; b < a.pending; b += 64) {
+            k += a.partial[2 * b];
+            t += a.partial[2 * b + 1];
+        }
+        k = wave_sum(k);
+        t = wave_sum(t);
+        if (tid == 0) {
+            a.grad[0] += k;
+            a.grad[1] += t;
+        }
+    }
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool own = gx < nx && gy < ny;
@@ -529,10 +547,13 @@ size_t adjoint_workspace_doubles(int nx, int ny) {
     return (size_t)adj::NFIELDS * (size_t)N + 2 * (size_t)blocks;
 }
 
-// kind: 0 step, 1 fields (rho_bar/u_bar given), 2 init
+// kind: 0 step, 1 fields (rho_bar/u_bar given), 2 init.  chain (steps of a
+// segment): kAdjPending = the previous step's partials are still to be added,
+// kAdjDeferReduce = leave this step's partials to the next step.
 hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int precision, int improved, const void* state,
                           const double* lam_in, double* lam_out, const double* rho_bar, const double* u_bar,
-                          const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s) {
+                          const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s,
+                          int chain) {
     adj::AdjArgs a;
     a.state = state;
     a.lam_in = lam_in;
@@ -550,6 +571,8 @@ hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int preci
     a.partial = ws + (size_t)adj::NFIELDS * a.N;
     a.improved = improved;
     a.precision = precision;
+    a.grad = grad;
+    a.pending = 0;
     const int B = 256, G = (a.N + B - 1) / B;
     if (kind == 2) {
         hipLaunchKernelGGL(adj::fwd_mu, dim3(G), dim3(B), 0, s, a, 1);
@@ -559,12 +582,14 @@ hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int preci
         return hipGetLastError();
     }
     const int tiles = ((a.nx + adj::TX - 1) / adj::TX) * ((a.ny + adj::TY - 1) / adj::TY);
+    a.pending = (chain & kAdjPending) ? tiles : 0;
     if (precision == 0)
         hipLaunchKernelGGL(adj::adj_front<double>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
     else
         hipLaunchKernelGGL(adj::adj_front<float>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
     hipLaunchKernelGGL(adj::adj_back, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
-    hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, tiles, grad);
+    if (!(chain & kAdjDeferReduce))
+        hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, tiles, grad);
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t adjoint_workspace_doubles(int nx, int ny);
 hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int precision, int improved, const void* state,
                           const double* lam_in, double* lam_out, const double* rho_bar, const double* u_bar,
-                          const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s);
+                          const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s,
+                          int chain);
 extern const int kD2Q9Shapes[][2];
 extern const int kNumD2Q9Shapes;
 extern const int kD3Q19Shapes[][2];
@@ -853,7 +854,7 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
     if (lam_next == lam_out) return fail(LBM_ERR_ARG, "lam_next and lam_out must not alias");
     HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, state_t, lam_next,
                            lam_out, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<double*>(ws), grad,
-                           h->stream));
+                           h->stream, 0));
     return LBM_OK;
 }
 
@@ -878,7 +879,8 @@ int enqueue_segment(lbm_ctx* h, int m, void* states, double* lam, double* lam2, 
     for (int k = m - 1; k >= 0; --k) {
         HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved,
                                st + (size_t)k * h->state_bytes, in, out, nullptr, nullptr, nullptr, nullptr,
-                               reinterpret_cast<double*>(ws), grad, s));
+                               reinterpret_cast<double*>(ws), grad, s,
+                               (k < m - 1 ? kAdjPending : 0) | (k > 0 ? kAdjDeferReduce : 0)));
         std::swap(in, out);
     }
     if (in != lam) HIP_TRY(launch_copy(lam, in, (size_t)9 * h->recs[0].nnodes * sizeof(double), s));
@@ -957,7 +959,7 @@ int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, c
     if (!state_t || !lam_out || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
     HIP_TRY(adjoint_launch(1, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, state_t, nullptr,
                            lam_out, rho_bar, u_bar, nullptr, nullptr, reinterpret_cast<double*>(ws), grad,
-                           h->stream));
+                           h->stream, 0));
     return LBM_OK;
 }
 
@@ -968,7 +970,7 @@ int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double*
     if (!rho0 || !lam0 || !grad_rho0 || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
     HIP_TRY(adjoint_launch(2, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, nullptr, lam0,
                            nullptr, nullptr, nullptr, rho0, grad_rho0, reinterpret_cast<double*>(ws), grad,
-                           h->stream));
+                           h->stream, 0));
     return LBM_OK;
 }
 

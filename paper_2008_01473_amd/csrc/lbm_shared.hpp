@@ -44,6 +44,9 @@ struct LatticeRec {
     double c0;                          // improved scheme: p_m = (c0 + mu)/3 (the paper: 1)
 };
 
+// Chaining flags of consecutive adjoint steps (adjoint_launch).
+enum AdjChain : int { kAdjPending = 1, kAdjDeferReduce = 2 };
+
 // One unit of work: an output tile (2D) or an output column chunk (3D).  It also
 // carries its lattice's extents, wrap flags and state offset, so that a batch's
 // tile can issue its pulls as soon as this record has arrived.
