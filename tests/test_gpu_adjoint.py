@@ -232,13 +232,16 @@ def test_full_size_adjoint_config_against_finite_differences():
     assert max(errs32) < 1e-2
 
 
-@pytest.mark.parametrize("m", [1, 5])
-def test_adjoint_segment_equals_step_by_step(m):
+@pytest.mark.parametrize("m,graphs", [(1, True), (5, True), (5, False)])
+def test_adjoint_segment_equals_step_by_step(m, graphs):
     """lbm_adjoint_segment (restore, recompute m states, m adjoint steps) gives
-    the same lambda and parameter gradients as doing it call by call."""
+    the same lambda and parameter gradients as doing it call by call, bit for bit,
+    launched eagerly or replayed from its captured graph (second call), and
+    leaves the handle at time level t0 + m with that state."""
     p, rho0 = _case("improved")
     roll = Rollout(p)
     sim = roll.sim
+    sim.use_graphs(graphs)
     L = _lib.lib()
     sim.init(rho0)
     sim.step(3)
@@ -256,14 +259,20 @@ def test_adjoint_segment_equals_step_by_step(m):
         _lib.check(L.lbm_adjoint_step(sim.h, s.data_ptr(), lam.data_ptr(), lam2.data_ptr(), roll.ws.data_ptr(),
                                       g1.data_ptr()))
         lam, lam2 = lam2, lam
-    # one call
+    end_state = sim.get_state()[0].clone()
+    # one call, twice on the same buffers (the second replays the captured graph)
     states = torch.empty(m * sim.state_bytes, dtype=torch.uint8, device="cuda")
-    lam_b, lam_b2 = lam0.clone(), torch.empty_like(lam0)
+    lam_b, lam_b2 = torch.empty_like(lam0), torch.empty_like(lam0)
     g2 = torch.zeros(2, dtype=torch.float64, device="cuda")
-    _lib.check(L.lbm_adjoint_segment(sim.h, ck.data_ptr(), t0, m, states.data_ptr(), lam_b.data_ptr(),
-                                     lam_b2.data_ptr(), roll.ws.data_ptr(), g2.data_ptr()))
-    torch.cuda.synchronize()
-    assert torch.equal(lam_b, lam)
-    assert torch.equal(g1, g2)
-    assert sim.time == t0 + m
+    for rep in range(2):
+        print(f"case adjoint segment m={m} graphs={graphs} call {rep}", flush=True)
+        lam_b.copy_(lam0)
+        g2.zero_()
+        _lib.check(L.lbm_adjoint_segment(sim.h, ck.data_ptr(), t0, m, states.data_ptr(), lam_b.data_ptr(),
+                                         lam_b2.data_ptr(), roll.ws.data_ptr(), g2.data_ptr()))
+        torch.cuda.synchronize()
+        assert torch.equal(lam_b, lam)
+        assert torch.equal(g1, g2)
+        assert sim.time == t0 + m
+        assert torch.equal(sim.get_state()[0], end_state)
     roll.close()
