@@ -933,7 +933,6 @@ int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m,
     if (lam == lam2) return fail(LBM_ERR_ARG, "lam and lam2 must not alias");
     if (((uintptr_t)states | (uintptr_t)lam | (uintptr_t)lam2 | (uintptr_t)checkpoint) & 15)
         return fail(LBM_ERR_ARG, "checkpoint, states, lam and lam2 must be 16-byte aligned");
-    if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
     rc = reset_status(h);
     if (rc != LBM_OK) return rc;
     HIP_TRY(launch_copy(states, checkpoint, h->state_bytes, h->stream));

@@ -126,3 +126,45 @@ def test_batch_offsets_are_dense():
     assert [L.lbm_node_offset(h, i) for i in range(3)] == [0, 256, 256 + 576]
     assert L.lbm_num_nodes(h) == 256 + 576 + 1600
     L.lbm_destroy(h)
+
+
+def test_adjoint_workspace_covers_its_tiles():
+    """The adjoint workspace holds 26 float64 fields per node and two partial
+    sums per work group of its tile kernels (32 x 8 nodes) or per 256-node block,
+    whichever is more: a ragged lattice can have more tiles than blocks."""
+    L = lib()
+    for nx, ny in [(33, 9), (70, 45), (256, 256), (20, 24)]:
+        rc, h = _create(runtime.params(nx=nx, ny=ny))
+        assert rc == 0
+        n = nx * ny
+        tiles = -(-nx // 32) * -(-ny // 8)
+        need = 8 * (26 * n + 2 * max(-(-n // 256), tiles))
+        assert L.lbm_adjoint_workspace_bytes(h) >= need
+        assert L.lbm_adjoint_workspace_bytes(h) % 256 == 0
+        L.lbm_destroy(h)
+    for kw in (dict(lattice="D3Q19", nz=8), dict(collision="mrt", tau_e=1.0, tau_s=1.0, tau_q=1.0),
+               dict(walls=(0.01, 0.0))):
+        args = dict(lattice="D2Q9", nx=16, ny=16, nz=1)
+        args.update(kw)
+        rc, h = _create(runtime.params(**args))
+        assert rc == 0
+        assert L.lbm_adjoint_workspace_bytes(h) == 0
+        L.lbm_destroy(h)
+
+
+def test_adjoint_and_copy_entry_points_reject_before_touching_memory():
+    """Unbound handles, unsupported lattices and misaligned or null pointers are
+    refused on the host; the pointers below are never dereferenced."""
+    L = lib()
+    rc, h = _create(runtime.params(nx=16, ny=16))
+    assert rc == 0
+    fake = ctypes.c_void_p(0x1000)
+    buf = ctypes.cast(fake, ctypes.POINTER(ctypes.c_double))
+    assert L.lbm_adjoint_segment(h, fake, 0, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_STATE
+    assert L.lbm_adjoint_step(h, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_STATE
+    L.lbm_destroy(h)
+    rc, h = _create(runtime.params(lattice="D3Q19", nx=8, ny=8, nz=8))
+    assert L.lbm_adjoint_segment(h, fake, 0, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_UNSUPPORTED
+    L.lbm_destroy(h)
+    assert L.lbm_copy_kernel(ctypes.c_void_p(0x1004), fake, 64, None) == lib_mod.LBM_ERR_ARG
+    assert L.lbm_copy_kernel(None, fake, 64, None) == lib_mod.LBM_ERR_ARG
