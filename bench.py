@@ -359,8 +359,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'Sharding'); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (lattices of a batch are "
+              "independent and would be split between GPUs by the caller); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -52,7 +52,7 @@ extern "C" {
 enum lbm_status_code {
     LBM_OK = 0,
     LBM_ERR_ARG = -1,          /* invalid argument or parameter combination        */
-    LBM_ERR_UNSUPPORTED = -2,  /* valid request this build does not implement      */
+    LBM_ERR_UNSUPPORTED = -2,  /* valid request the library does not implement    */
     LBM_ERR_HIP = -3,          /* a HIP runtime call failed                        */
     LBM_ERR_BLOWUP = -4,       /* a lattice produced NaN/Inf or left the EOS domain */
     LBM_ERR_DOMAIN = -5,       /* no liquid-gas coexistence (e.g. T >= T_c)        */
