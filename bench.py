@@ -222,6 +222,19 @@ def d3q19_spec(runtime, inputs, T=0.85):
                         "fp32 deviation storage"}
 
 
+def d3q19_shard_spec(runtime, inputs, T=0.85):
+    """One GPU's share of the 256^3 droplet split into 8 slabs along z: 256 x 256 x 32,
+    the slab through the droplet's centre, periodic in z (standing in for the
+    neighbours' faces; the face exchange itself is not part of a one-GPU step)."""
+    m = runtime.maxwell("vdW", T)
+    p = runtime.params("D3Q19", 256, 256, 32, eos="vdW", T_over_Tc=T, kappa=0.02, tau=1.0,
+                       scheme="improved", precision="fp32")
+    rho0 = inputs.droplet((256, 256, 256), m["rho_g"], m["rho_l"], 40.0, 5.0, noise=0.0)[112:144].copy()
+    return {"name": "d3q19_256x256x32_shard_fp32", "params": [p], "rho0": rho0,
+            "workload": f"D3Q19 256x256x32 (one of 8 z-slabs of the 256^3 vdW droplet, periodic in z), T/Tc={T}, "
+                        "kappa=0.02, tau=1.0, improved, fp32 deviation storage"}
+
+
 def batch_spec(runtime, inputs, count=96, seed=0):
     specs = inputs.batch_specs(count, seed)
     ps, rhos = [], []
@@ -396,6 +409,7 @@ def main():
             # the standard scheme blows up for this droplet at T/Tc = 0.8 (oracle too); 0.9 is stable
             ("standard", lambda: primary_spec(runtime, inputs, scheme="standard", T=0.9), args.steps),
             ("d3q19", lambda: d3q19_spec(runtime, inputs), max(20, args.steps // 40)),
+            ("d3q19_shard", lambda: d3q19_shard_spec(runtime, inputs), max(20, args.steps // 10)),
             ("d2q9_4096_fp64", lambda: d2q9_large_spec(runtime, inputs, "fp64"), max(20, args.steps // 40)),
             ("d2q9_4096_fp32", lambda: d2q9_large_spec(runtime, inputs, "fp32"), max(20, args.steps // 40)),
             ("batch", lambda: batch_spec(runtime, inputs), max(20, args.steps // 20)),
