@@ -348,8 +348,19 @@ def cpu_baseline(torch, inputs, seconds):
     from oracle import eos as oeos
     from oracle import model
 
-    threads = os.cpu_count() or 1
+    # the CPUs this process may run on (capped by OMP_NUM_THREADS when it is set)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     torch.set_num_threads(threads)
+    model_name = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model_name = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     E = oeos.CarnahanStarling()
     m = oeos.maxwell(E, 0.8)
     rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
@@ -365,7 +376,7 @@ def cpu_baseline(torch, inputs, seconds):
             break
     return {"value": 512 * 512 * n / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
             "kind": "oracle", "sample": f"{n} steps of the 512x512 D2Q9 CS droplet (improved, float64), "
-                                        f"{el:.1f} s on the host CPU"}
+                                        f"{el:.1f} s on {torch.get_num_threads()} threads of {model_name}"}
 
 
 def main():
