@@ -165,9 +165,10 @@ def _droplet_shape(rho, rg, rl):
 def test_moving_droplet_between_plates_stays_circular():
     """Sec. IV B's Galilean-invariance test: 120 x 120 channel, droplet r = 25 at the
     centre, both plates moving at U = 0.1 from t = 0, T/Tc = 0.7, constant nu = 0.15
-    (MRT, tau_e = tau_s = tau_q = 1).  With the paper's c0 = 1 this lattice blows up
-    (the gas rest population of Eq. 27 is negative at T/Tc = 0.7); with c0 = 0.6 the
-    droplet is carried along by the flow and stays circular (Fig. 6)."""
+    (MRT, tau_e = tau_s = tau_q = 1), to Fig. 6's last snapshot at t = 9e4.  With the
+    paper's c0 = 1 this lattice blows up (the gas rest population of Eq. 27 is negative
+    at T/Tc = 0.7); with c0 = 0.6 the droplet is carried along by the flow and stays
+    circular (Fig. 6)."""
     m = oeos.maxwell(oeos.make_eos("vdW"), 0.7)
     rho0 = inputs.droplet((120, 120), m["rho_g"], m["rho_l"], 25.0, 5.0)
     res = {}
@@ -178,8 +179,9 @@ def test_moving_droplet_between_plates_stays_circular():
         sim = runtime.LBM(p)
         sim.init(rho0)
         mass0, track, t = None, [], 0
-        # shape every 4000 steps, then the centre every 500 steps (50 units < half the period)
-        for target in [0, 4000, 8000, 12000, 16000] + list(range(16500, 20001, 500)):
+        # shape at Fig. 6's snapshot times, then the centre every 500 steps (under half
+        # the period at any speed up to U)
+        for target in [0, 20000, 40000, 70000, 86000] + list(range(86500, 90001, 500)):
             sim.step(target - t)
             t = target
             rho, _, _ = sim.moments()
@@ -193,14 +195,18 @@ def test_moving_droplet_between_plates_stays_circular():
         sim.close()
     assert res[1.0][0] != 0                      # blown up and flagged
     status, track = res[0.6]
-    assert status == 0 and track[-1][0] == 20000
-    for _, _, aspect, req in track:
+    assert status == 0 and track[-1][0] == 90000
+    for t, _, aspect, req in track:
+        print(f"  t {t}: aspect {aspect:.4f}, radius {req:.3f}", flush=True)
         assert aspect < 1.02
         assert req == pytest.approx(track[0][3], rel=0.02)
-    late = [tr for tr in track if tr[0] >= 16000]
+    late = [tr for tr in track if tr[0] >= 86000]
     dist = sum((b[1] - a[1]) % 120 for a, b in zip(late, late[1:]))
     speed = dist / (late[-1][0] - late[0][0])
-    print(f"droplet speed {speed:.4f}, final aspect {track[-1][2]:.4f}", flush=True)
-    # the plates' momentum reaches the channel centre on the viscous time ny^2 / nu ~ 1e5
-    # steps (Fig. 6 runs to 9e4), so at t = 2e4 the droplet moves forward, slower than U
-    assert 0.003 < speed < 0.1
+    print(f"droplet speed {speed:.4f} at t = 9e4", flush=True)
+    # The droplet is carried forward but settles (by t ~ 2e4) at a steady 0.0076, not U:
+    # the net interfacial force of a translating droplet, -sum rho grad mu with the
+    # force of Eq. 24, opposes its motion and balances the shear the plates transmit
+    # through the gas (the oracle shows the same; the pressure-tensor form conserves
+    # momentum exactly).  Fig. 6 claims the shape, which holds.
+    assert 0.004 < speed < 0.015
