@@ -210,7 +210,9 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu);
  * Lattices it reports blown up leave the launch plan (their populations stay
  * frozen and no work group is spent on them; captured graphs are re-captured
  * on the next lbm_step) until lbm_init, lbm_set_f or lbm_set_state clears the
- * flags; repeated calls before the next step return the same values. */
+ * flags; repeated calls before the next step return the same values, and a
+ * lattice out of the plan keeps reporting the diagnostics (and step) it had
+ * when it was reported. */
 int lbm_diagnostics(lbm_ctx* h, lbm_diag* out_host);
 
 /* Populations f_a(x, t) at the current time level as float64 (layout above),

@@ -99,6 +99,8 @@ struct lbm_ctx {
     // until the next reset of the status flags.  Their last diagnostics stay
     // readable from a host copy until the next step produces new ones.
     std::vector<char> dropped;
+    std::vector<DiagOut> frozen_diag;       // a dropped lattice's diagnostics when it was reported
+    std::vector<long long> frozen_step;
     std::vector<DiagOut> diag_cache;
     bool diag_cache_valid = false;
 
@@ -475,6 +477,8 @@ int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx**
         h->recs.push_back(R);
     }
     h->dropped.assign(count, 0);
+    h->frozen_diag.assign(count, DiagOut{});
+    h->frozen_step.assign(count, -1);
     h->field_total = foff;
     h->state_nodes = soff;
     const size_t word = h->precision == LBM_FP64 ? 8 : 4;
@@ -629,6 +633,8 @@ int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
         for (int i = 0; i < n; ++i) {
             if (!tmp[i].status || h->dropped[i]) continue;
             h->dropped[i] = fresh = true;
+            h->frozen_diag[i] = tmp[i];
+            h->frozen_step[i] = h->t_diag;
             const LatticeRec& R = h->recs[i];
             const size_t off = (size_t)R.state_offset * h->Q * word;
             const size_t len = (size_t)((R.nnodes + 63) / 64 * 64) * h->Q * word;
@@ -644,17 +650,19 @@ int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
     }
     int rc = LBM_OK;
     for (int i = 0; i < n; ++i) {
-        out[i].mass = tmp[i].mass;
-        out[i].mom[0] = tmp[i].momx;
-        out[i].mom[1] = tmp[i].momy;
-        out[i].mom[2] = tmp[i].momz;
-        out[i].max_u = tmp[i].umax;
-        out[i].mu_min = tmp[i].mumin;
-        out[i].mu_max = tmp[i].mumax;
-        out[i].step = h->t_diag;
-        out[i].status = (int)tmp[i].status;
+        // a lattice out of the plan has no tiles: it reports what it had when it left
+        const DiagOut& d = h->dropped[i] ? h->frozen_diag[i] : tmp[i];
+        out[i].mass = d.mass;
+        out[i].mom[0] = d.momx;
+        out[i].mom[1] = d.momy;
+        out[i].mom[2] = d.momz;
+        out[i].max_u = d.umax;
+        out[i].mu_min = d.mumin;
+        out[i].mu_max = d.mumax;
+        out[i].step = h->dropped[i] ? h->frozen_step[i] : h->t_diag;
+        out[i].status = (int)(d.status | tmp[i].status);
         out[i].reserved = 0;
-        if (tmp[i].status) rc = LBM_ERR_BLOWUP;
+        if (out[i].status) rc = LBM_ERR_BLOWUP;
     }
     if (rc != LBM_OK) fail(rc, "at least one lattice has its blow-up flags set");
     return rc;

@@ -237,6 +237,8 @@ def test_reported_blowup_leaves_the_plan_until_reinit():
     assert torch.equal(sim.get_f()[:, off:].cpu(), solo.get_f().cpu())
     d2 = sim.diagnostics()
     assert d2[0]["status"] != 0 and d2[1]["status"] == 0 and d2[1]["step"] == 24
+    # the frozen lattice keeps the diagnostics it had when it was reported
+    assert d2[0]["step"] == d1[0]["step"] and repr(d2[0]["mass"]) == repr(d1[0]["mass"])
     assert d2[1]["mass"] == pytest.approx(float(good.sum()), rel=1e-13)
     # re-initialised with a sound state, both lattices run again
     other = _droplet((32, 32), "vdW", 0.8, 7.0, seed=3)
