@@ -747,6 +747,8 @@ int lbm_set_tile_shape(lbm_ctx* h, int s) {
         h->shape_dims(s, bx, by);
         if (h->lattice == LBM_D3Q19 && h->precision == LBM_FP64 && bx * by > 256)
             return fail(LBM_ERR_UNSUPPORTED, "this D3Q19 tile shape needs more LDS than float64 allows");
+        if (h->lattice == LBM_D2Q9 && h->precision == LBM_FP64 && bx * by > 1024)
+            return fail(LBM_ERR_UNSUPPORTED, "this D2Q9 tile shape (two nodes per thread) is float32 only");
     }
     std::vector<LatticeRec> rr = h->recs;
     std::vector<Tile> tt = h->plan(s, rr);
@@ -785,7 +787,11 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     float best_ms = 1e30f;
     for (int s = 0; s < h->num_shapes(); ++s) {
         rc = lbm_set_tile_shape(h, s);
-        if (rc != LBM_OK) continue;
+        if (rc == LBM_ERR_UNSUPPORTED) {       // a shape this lattice or precision does not offer
+            rc = LBM_OK;
+            continue;
+        }
+        if (rc != LBM_OK) break;
         rc = lbm_step(h, 2);                 // warm-up and graph capture
         if (rc != LBM_OK) break;
         HIP_TRY(hipEventRecord(e0, h->stream));

@@ -219,19 +219,20 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 // diagnostics, or writing rho, u, mu of the current time level.
 // FEAT bit 1: lattices of the launch may use the MRT collision; bit 2: they may
 // have plates (the lattice record decides); launches without them carry no such code.
-template <typename S, typename T, int V, int BX, int BY, int MODE, int FEAT>
+template <typename S, typename T, int V, int BX, int BY, int MODE, int FEAT, int NPT>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
+    constexpr int TH = BY * NPT, NN = BX * TH;     // tile: BX x TH nodes, NPT per thread (rows BY apart)
     constexpr bool MRT = (FEAT & 1) != 0;
     constexpr bool PLATES = (FEAT & 2) != 0;
-    constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
+    constexpr int W3 = BX + 6, H3 = TH + 6, W2 = BX + 4, H2 = TH + 4, W1 = BX + 2, H1 = TH + 2;
     constexpr bool IMP = (V == kImproved);
     constexpr bool PT = (V == kStdPtensor);
     __shared__ T s_rho[H3 * W3];
     __shared__ T s_mu[H2 * W2];
     __shared__ T s_a[H1 * W1];            // j_x, then psi_x = phi u_x
     __shared__ T s_b[H1 * W1];            // j_y, then psi_y
-    __shared__ T s_F[2 * NT], s_u[2 * NT];
+    __shared__ T s_F[2 * NN], s_u[2 * NN];
     __shared__ T s_P[PT ? 3 * H2 * W2 : 1];
     __shared__ double s_red[7 * (NT / 64)];
     __shared__ unsigned s_ured[NT / 64];
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         band_order(t_idx, args.ntx, args.nty, args.band, tx, ty);
         lat = 0;
         x0 = tx * BX;
-        y0 = ty * BY;
+        y0 = ty * TH;
         nx = args.nx0;
         ny = args.ny0;
         sx = args.slow_x0;
@@ -280,27 +281,29 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     // ---- stage A: the interior node owned by this thread (kept in registers for
     // stage D) and up to HP nodes of the three halo rings; every load is issued
     // before any is used.
-    constexpr int HALO = H3 * W3 - NT;
+    constexpr int HALO = H3 * W3 - NN;
     constexpr int HP = (HALO + NT - 1) / NT;
-    T fown[9];
+    T fown[NPT][9];
     T fh[HP][9];
     int hpos[HP];
     const bool plates = PLATES && R.walls;
     // A tile whose pulls (tile + 4 rings) stay inside the lattice needs no periodic
     // wrap: block-uniform, so the wrap arithmetic is skipped for most tiles.
-    const bool inner = x0 >= 4 && x0 + BX + 4 <= nx && y0 >= 4 && y0 + BY + 4 <= ny;
+    const bool inner = x0 >= 4 && x0 + BX + 4 <= nx && y0 >= 4 && y0 + TH + 4 <= ny;
     auto wx = [&](int v) { return inner ? v : wrap(v, nx, sx); };
     auto wy = [&](int v) { return inner ? v : wrap(v, ny, sy); };
-    bool own_mirror = false;
+    bool own_mirror[NPT];
     bool h_mirror[HP];
-    {
-        const int gx = x0 + lx0, gy = y0 + ly0;
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int gx = x0 + lx0, gy = y0 + ly0 + p * BY;
         const int xc = wx(gx), xm = wx(gx - 1), xp = wx(gx + 1);
+        own_mirror[p] = false;
         if (plates) {
-            pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, own_mirror), fown);
+            pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, own_mirror[p]), fown[p]);
         } else {
             const int yc = wy(gy), ym = wy(gy - 1), yp = wy(gy + 1);
-            pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown);
+            pull<S, T>(pp, nx, xm, xc, xp, ym, yc, yp, fown[p]);
         }
     }
 #pragma unroll
@@ -339,9 +342,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     __shared__ unsigned s_skip;
     if (tid == 0) s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
     // a mirror image beyond a plate carries the reflected momentum (j_y negated)
-    s_rho[(ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown);
-    s_a[(ly0 + 1) * W1 + lx0 + 1] = jx9(fown);
-    s_b[(ly0 + 1) * W1 + lx0 + 1] = own_mirror ? -jy9(fown) : jy9(fown);
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int ly = ly0 + p * BY;
+        s_rho[(ly + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown[p]);
+        s_a[(ly + 1) * W1 + lx0 + 1] = jx9(fown[p]);
+        s_b[(ly + 1) * W1 + lx0 + 1] = own_mirror[p] ? -jy9(fown[p]) : jy9(fown[p]);
+    }
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
         if (tid + q * NT < HALO) {
@@ -403,25 +410,29 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             s_a[k] = phi * ux;
             s_b[k] = phi * uy;
         }
-        if (lx >= 1 && lx <= BX && ly >= 1 && ly <= BY) {
+        if (lx >= 1 && lx <= BX && ly >= 1 && ly <= TH) {
             const int i0 = (ly - 1) * BX + lx - 1;
-            s_F[i0] = Fx; s_F[NT + i0] = Fy;
-            s_u[i0] = ux; s_u[NT + i0] = uy;
+            s_F[i0] = Fx; s_F[NN + i0] = Fy;
+            s_u[i0] = ux; s_u[NN + i0] = uy;
         }
     }
     __syncthreads();
 
     // ---- stage D: collide and store (or write fields) ----
     DiagAcc acc;
-    const int gx = x0 + lx0, gy = y0 + ly0;
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+    T (&fo)[9] = fown[p];
+    const int ly = ly0 + p * BY, io = tid + p * NT;
+    const int gx = x0 + lx0, gy = y0 + ly;
     if (gx < nx && gy < ny) {
-        const int c3 = (ly0 + 3) * W3 + lx0 + 3, c2 = (ly0 + 2) * W2 + lx0 + 2, c1 = (ly0 + 1) * W1 + lx0 + 1;
+        const int c3 = (ly + 3) * W3 + lx0 + 3, c2 = (ly + 2) * W2 + lx0 + 2, c1 = (ly + 1) * W1 + lx0 + 1;
         const T r = s_rho[c3];
         const T mu = s_mu[c2];
-        const T Fx = s_F[tid], Fy = s_F[NT + tid], ux = s_u[tid], uy = s_u[NT + tid];
-        const T drho = sum9(fown);
+        const T Fx = s_F[io], Fy = s_F[NN + io], ux = s_u[io], uy = s_u[NN + io];
+        const T drho = sum9(fo);
         constexpr bool F32 = sizeof(S) == 4;
-        const double m_in = F32 ? mass_in<9, T>(fown) : 0.0;      // exact node mass (float32 storage)
+        const double m_in = F32 ? mass_in<9, T>(fo) : 0.0;      // exact node mass (float32 storage)
         const int node = gy * nx + gx;
         if constexpr (MODE == kFields) {
             const long long o = R.field_offset + node;
@@ -451,11 +462,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     const T nu = (T)R.nu;
                     s_v = IMP ? dev_rcp(nu * r * dev_rcp(pm_ref + dpm) + T(0.5)) : dev_rcp(T(3) * nu + T(0.5));
                 }
-                collide_mrt<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
+                collide_mrt<T>(fo, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
             } else {
-                collide<T>(fown, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+                collide<T>(fo, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
             }
-            if constexpr (F32) keep_mass_on_axes<9, 4, T>(fown, m_in);
+            if constexpr (F32) keep_mass_on_axes<9, 4, T>(fo, m_in);
             if (plates && (gy == 0 || gy == ny - 1)) {
                 // Populations heading into a plate are stored reflected for the next pull:
                 // f*_a + feq_-a - feq_a at the plate velocity U (along x).  The odd part of
@@ -464,25 +475,26 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 const T pm = IMP ? pm_ref + dpm : r * T(1.0 / 3.0);
                 if (gy == 0) {
                     const T w = T(0.5) * pm * (T)R.wall_u0;
-                    fown[7] += w;              // SW returns as NE
-                    fown[8] -= w;              // SE returns as NW
+                    fo[7] += w;              // SW returns as NE
+                    fo[8] -= w;              // SE returns as NW
                 }
                 if (gy == ny - 1) {
                     const T w = T(0.5) * pm * (T)R.wall_u1;
-                    fown[5] -= w;              // NE returns as SW
-                    fown[6] += w;              // NW returns as SE
+                    fo[5] -= w;              // NE returns as SW
+                    fo[6] += w;              // NW returns as SE
                 }
             }
 #pragma unroll
-            for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fown[a]);
+            for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
         }
-        acc.mass = F32 ? m_in : (double)drho;
-        acc.mx = (double)(r * ux);
-        acc.my = (double)(r * uy);
-        acc.umax2 = (double)(ux * ux + uy * uy);
-        acc.mumin = (double)mu;
-        acc.mumax = (double)mu;
-        acc.status = blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
+        acc.mass += F32 ? m_in : (double)drho;
+        acc.mx += (double)(r * ux);
+        acc.my += (double)(r * uy);
+        acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
+        acc.mumin = fmin(acc.mumin, (double)mu);
+        acc.mumax = fmax(acc.mumax, (double)mu);
+        acc.status |= blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
+    }
     }
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + lat, acc.status);
@@ -584,38 +596,38 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 // Host-side launchers (called by the runtime).
 
 namespace {
-template <typename S, typename T, int V, int BX, int BY, int MODE>
+template <typename S, typename T, int V, int BX, int BY, int MODE, int NPT>
 void launch_feat(const StepArgs& a, int feat, dim3 g, dim3 b, hipStream_t s) {
     switch (feat) {
-        case 1: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 1>), g, b, 0, s, a); return;
+        case 1: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 1, NPT>), g, b, 0, s, a); return;
         case 2:
             if constexpr (V != kStdPtensor)      // plates are not offered with the pressure-tensor force
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 2>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 2, NPT>), g, b, 0, s, a);
             return;
         case 3:
             if constexpr (V != kStdPtensor)
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 3>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 3, NPT>), g, b, 0, s, a);
             return;
-        default: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 0>), g, b, 0, s, a); return;
+        default: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 0, NPT>), g, b, 0, s, a); return;
     }
 }
 
-template <typename S, typename T, int V, int BX, int BY>
+template <typename S, typename T, int V, int BX, int BY, int NPT = 1>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
     const dim3 g(grid), b(BX * BY);
     const int feat = (a.any_mrt ? 1 : 0) | (a.any_plates ? 2 : 0);
     if (mode == kFields) {
         if constexpr (V != kStdPtensor) {
             if (a.any_plates) {
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 2>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 2, NPT>), g, b, 0, s, a);
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0>), g, b, 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0, NPT>), g, b, 0, s, a);
     } else if (mode == kStepDiag) {
-        launch_feat<S, T, V, BX, BY, kStepDiag>(a, feat, g, b, s);
+        launch_feat<S, T, V, BX, BY, kStepDiag, NPT>(a, feat, g, b, s);
     } else {
-        launch_feat<S, T, V, BX, BY, kStep>(a, feat, g, b, s);
+        launch_feat<S, T, V, BX, BY, kStep, NPT>(a, feat, g, b, s);
     }
     return hipGetLastError();
 }
@@ -629,15 +641,18 @@ hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, int fields, 
         case 3: return launch_step_t<S, T, V, 16, 16>(a, grid, s, fields);
         case 4: return launch_step_t<S, T, V, 64, 16>(a, grid, s, fields);
         case 5: return launch_step_t<S, T, V, 128, 8>(a, grid, s, fields);
+        case 6:    // 128 x 16 nodes, two per thread: float32 only (float64 exceeds the LDS)
+            if constexpr (sizeof(S) == 4) return launch_step_t<S, T, V, 128, 8, 2>(a, grid, s, fields);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
 extern const int kD2Q9Shapes[][2];
-const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}};
+const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}, {128, 16}};
 extern const int kNumD2Q9Shapes;
-const int kNumD2Q9Shapes = 6;
+const int kNumD2Q9Shapes = 7;
 
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
                             int fields) {

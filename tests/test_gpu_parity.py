@@ -254,6 +254,32 @@ def test_reported_blowup_leaves_the_plan_until_reinit():
         x.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_restores_state_and_skips_shapes_the_precision_lacks(prec):
+    """lbm_autotune times every tile shape the lattice offers (float64 has no
+    two-nodes-per-thread D2Q9 shape), keeps the fastest, and leaves the state, the
+    time level and the results of the next steps as they were."""
+    p = runtime.params("D2Q9", 96, 80, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec)
+    rho0 = _droplet((80, 96), "vdW", 0.8, 15.0)
+    print(f"case autotune {prec}", flush=True)
+    ref = runtime.LBM(p)
+    ref.init(rho0)
+    ref.step(9)
+    sim = runtime.LBM(p)
+    sim.init(rho0)
+    sim.step(4)
+    best = sim.autotune(3)
+    assert 0 <= best < sim.num_tile_shapes()
+    assert runtime._lib.lib().lbm_get_tile_shape(sim.h) == best
+    if prec == "fp64":
+        assert sim.tile_shape()[0] * sim.tile_shape()[1] <= 1024
+    assert sim.time == 4
+    sim.step(5)
+    assert torch.equal(sim.get_f(), ref.get_f())
+    ref.close()
+    sim.close()
+
+
 def test_state_round_trips_and_zero_steps():
     p = runtime.params("D2Q9", 30, 20, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8)
     rho0 = _droplet((20, 30), "vdW", 0.8, 6.0)

@@ -88,14 +88,20 @@ def test_plates_fp32_deviation_storage(scheme):
     sim.close()
 
 
-def test_plates_every_tile_shape_gives_identical_populations():
-    p = runtime.params("D2Q9", 45, 37, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, walls=PLATES)
+@pytest.mark.parametrize("prec,extra", [("fp64", {}), ("fp32", {}),
+                                        ("fp32", dict(collision="mrt", tau_e=1.1, tau_s=1.3, tau_q=0.9, nu=0.1))])
+def test_plates_every_tile_shape_gives_identical_populations(prec, extra):
+    p = runtime.params("D2Q9", 45, 37, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, walls=PLATES, precision=prec, **extra)
     rho0 = _droplet((37, 45), "vdW", 0.8, 8.0)
     sim = runtime.LBM(p)
     outs = []
     for s in range(sim.num_tile_shapes()):
-        print(f"case plates tile shape {s}", flush=True)
-        sim.set_tile_shape(s)
+        print(f"case plates {prec} {'mrt' if extra else 'bgk'} tile shape {s}", flush=True)
+        try:
+            sim.set_tile_shape(s)
+        except runtime._lib.LBMError as e:
+            assert e.code == runtime._lib.LBM_ERR_UNSUPPORTED
+            continue
         sim.init(rho0)
         sim.step(7)
         outs.append(sim.get_f().cpu())
