@@ -289,10 +289,11 @@ double lbm_critical_temperature(int eos, double a, double b, double R);
  * [0, lbm_num_tile_shapes) names the output tile of one work group, bx x by
  * nodes; for D3Q19 it also fixes the z-chunk bz each work group sweeps (the same
  * xy tile appears with several chunk lengths).  lbm_describe_tile_shape reports
- * (bx, by, bz); bz is 1 for D2Q9.  A D2Q9 tile of more than 1024 nodes has
- * each thread own two nodes and exists in float32 only; it and some D3Q19
- * float64 shapes return LBM_ERR_UNSUPPORTED in float64 (LDS), and lbm_autotune
- * skips them.  Re-tiling synchronises the handle's stream. */
+ * (bx, by, bz); for D2Q9, bz is the number of nodes each thread owns (1 or 2,
+ * rows by / bz apart; work groups of bx * by / bz threads).  The 2048-node D2Q9
+ * tile exists in float32 only; it and some D3Q19 float64 shapes return
+ * LBM_ERR_UNSUPPORTED in float64 (LDS), and lbm_autotune skips them.  Re-tiling
+ * synchronises the handle's stream. */
 int lbm_set_tile_shape(lbm_ctx* h, int shape_index);
 int lbm_get_tile_shape(const lbm_ctx* h);
 int lbm_num_tile_shapes(const lbm_ctx* h);

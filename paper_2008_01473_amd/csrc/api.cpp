@@ -43,6 +43,7 @@ hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int preci
                           int chain);
 extern const int kD2Q9Shapes[][2];
 extern const int kNumD2Q9Shapes;
+extern const int kD2Q9NodesPerThread[];
 extern const int kD3Q19Shapes[][2];
 extern const int kNumD3Q19Shapes;
 }  // namespace lbm
@@ -736,7 +737,7 @@ int lbm_describe_tile_shape(const lbm_ctx* h, int s, int* bx, int* by, int* bz) 
     h->shape_dims(s, x, y);
     if (bx) *bx = x;
     if (by) *by = y;
-    if (bz) *bz = h->zchunk_for(s);
+    if (bz) *bz = h->lattice == LBM_D2Q9 ? kD2Q9NodesPerThread[s] : h->zchunk_for(s);
     return LBM_OK;
 }
 

@@ -644,15 +644,18 @@ hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, int fields, 
         case 6:    // 128 x 16 nodes, two per thread: float32 only (float64 exceeds the LDS)
             if constexpr (sizeof(S) == 4) return launch_step_t<S, T, V, 128, 8, 2>(a, grid, s, fields);
             return hipErrorInvalidValue;
+        case 7: return launch_step_t<S, T, V, 64, 8, 2>(a, grid, s, fields);     // 64 x 16 nodes, two per thread
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
 extern const int kD2Q9Shapes[][2];
-const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}, {128, 16}};
+const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}, {128, 16}, {64, 16}};
 extern const int kNumD2Q9Shapes;
-const int kNumD2Q9Shapes = 7;
+const int kNumD2Q9Shapes = 8;
+extern const int kD2Q9NodesPerThread[];          // rows a thread owns, by / nodes-per-thread apart
+const int kD2Q9NodesPerThread[] = {1, 1, 1, 1, 1, 1, 2, 2};
 
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
                             int fields) {
