@@ -123,8 +123,9 @@ def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True, tune=0, ti
     if tile >= 0:
         sim.set_tile_shape(tile)
     elif tune:
-        sim.autotune(tune)          # times every tile shape on this state, keeps the fastest
+        sim.autotune(tune)          # times every tile shape (and store mode) on this state, keeps the fastest
     shape = sim.tile_shape()
+    stores = sim.store_mode()
     ms = timed_steps(torch, sim, steps, warmup)
     Q = sim.Q
     word = 8 if p_list[0].precision == 0 else 4
@@ -146,6 +147,7 @@ def measure(torch, runtime, inputs, spec, steps, warmup, graphs=True, tune=0, ti
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS},
         "tile": list(shape),
+        "stores": stores,
         "blown_up_lattices": blown,
         "live_lattices_at_start": live0,
         "max_u": max(d["max_u"] for d in diag),
@@ -407,8 +409,8 @@ def main():
     prim = measure(torch, runtime, inputs, primary_spec(runtime, inputs), args.steps, args.warmup, graphs, tune,
                    args.tile)
     prim["roofline"]["traffic"] = traffic_for(prim["name"], prim["tile"], sha, recs)
-    print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step",
-          file=sys.stderr, flush=True)
+    print(f"[bench] primary {prim['workload']}: {prim['mlups']:.1f} MLUPS, {prim['ms_per_step'] * 1e3:.2f} us/step"
+          f" (tile {prim['tile']}, {prim['stores']} stores)", file=sys.stderr, flush=True)
     secondary = []
     if not args.no_secondary:
         only = set(filter(None, args.only.split(",")))
@@ -443,8 +445,8 @@ def main():
             r["vs_primary_mlups"] = r["mlups"] / prim["mlups"]
             r["roofline"]["traffic"] = traffic_for(r["name"], r["tile"], sha, recs)
             secondary.append(r)
-            print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s)",
-                  file=sys.stderr, flush=True)
+            print(f"[bench] {name}: {r['mlups']:.1f} MLUPS ({r['roofline']['frac'] * 100:.1f}% of 8 TB/s;"
+                  f" tile {r['tile']}, {r['stores']} stores)", file=sys.stderr, flush=True)
     acc = None
     if not args.no_secondary and not args.no_accuracy and not args.no_graphs:
         acc = accuracy(torch, runtime, inputs)
@@ -471,7 +473,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": prim["workload"], "lattice": "D2Q9", "nodes": prim["nodes"],
-                   "bytes_per_lup": prim["bytes_per_lup"], "tile": prim["tile"]},
+                   "bytes_per_lup": prim["bytes_per_lup"], "tile": prim["tile"], "stores": prim["stores"]},
         "roofline": prim["roofline"],
         "copy_ceiling": ceiling,
         "accuracy": acc,

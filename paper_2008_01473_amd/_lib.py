@@ -17,6 +17,7 @@ LBM_STANDARD, LBM_IMPROVED = 0, 1
 LBM_FORCE_CHEMPOT, LBM_FORCE_PTENSOR = 0, 1
 LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_BGK, LBM_MRT = 0, 1
+LBM_STORES_STREAMING, LBM_STORES_DEVICE = 0, 1
 
 
 class lbm_params(ctypes.Structure):
@@ -72,6 +73,8 @@ SIGNATURES = {
     "lbm_num_tile_shapes": (c_int, [c_void_p]),
     "lbm_describe_tile_shape": (c_int, [c_void_p, c_int, P(c_int), P(c_int), P(c_int)]),
     "lbm_set_use_graphs": (c_int, [c_void_p, c_int]),
+    "lbm_set_store_mode": (c_int, [c_void_p, c_int]),
+    "lbm_get_store_mode": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p, c_int, c_void_p]),
     "lbm_copy_kernel": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lbm_error_string": (ctypes.c_char_p, [c_int]),

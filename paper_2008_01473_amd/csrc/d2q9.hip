@@ -484,8 +484,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     fo[6] += w;              // NW returns as SE
                 }
             }
+            if (args.write_through) {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
+                for (int a = 0; a < 9; ++a) st_dev(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
+            }
         }
         acc.mass += F32 ? m_in : (double)drho;
         acc.mx += (double)(r * ux);

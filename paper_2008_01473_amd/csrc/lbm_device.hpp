@@ -35,6 +35,17 @@ __device__ __forceinline__ void st_off(S* base, unsigned idx, S v) {
     __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(S)));
 }
 
+// Store at device scope: written through the L2 to the memory side during the
+// kernel, so nothing of it is left for the end-of-kernel write-back.  It pays for
+// a lattice whose two state buffers stay in the last-level cache between steps
+// (the write-back is then a large part of a short step); streaming lattices keep
+// the non-temporal stores above.
+template <typename S>
+__device__ __forceinline__ void st_dev(S* base, unsigned idx, S v) {
+    __hip_atomic_store(reinterpret_cast<S*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(S)), v,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Periodic wrap of a coordinate that is at most a few nodes outside [0, n).
 // `slow` is set by the host when n is too small for one conditional correction.
 __device__ __forceinline__ int wrap(int v, int n, int slow) {

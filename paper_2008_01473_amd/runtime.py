@@ -172,6 +172,16 @@ class LBM:
     def use_graphs(self, on=True):
         check(_lib.lib().lbm_set_use_graphs(self.h, 1 if on else 0))
 
+    _STORES = {"streaming": _lib.LBM_STORES_STREAMING, "device": _lib.LBM_STORES_DEVICE}
+
+    def set_store_mode(self, mode):
+        """"streaming" (non-temporal stores) or "device" (device-scope stores, D2Q9)."""
+        check(_lib.lib().lbm_set_store_mode(self.h, self._STORES[mode]), "lbm_set_store_mode")
+
+    def store_mode(self):
+        m = _lib.lib().lbm_get_store_mode(self.h)
+        return {v: k for k, v in self._STORES.items()}[m]
+
     def autotune(self, steps=20):
         scratch = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
         return check(_lib.lib().lbm_autotune(self.h, int(steps), scratch.data_ptr()), "lbm_autotune")

@@ -168,3 +168,25 @@ def test_adjoint_and_copy_entry_points_reject_before_touching_memory():
     L.lbm_destroy(h)
     assert L.lbm_copy_kernel(ctypes.c_void_p(0x1004), fake, 64, None) == lib_mod.LBM_ERR_ARG
     assert L.lbm_copy_kernel(None, fake, 64, None) == lib_mod.LBM_ERR_ARG
+
+
+def test_store_mode_selection_on_the_host():
+    """Streaming stores by default; device-scope stores are a D2Q9 option; bad
+    values are refused and leave the mode as it was (no GPU call involved)."""
+    L = lib()
+    rc, h = _create(runtime.params(nx=16, ny=16))
+    assert rc == 0
+    assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_STREAMING
+    assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_DEVICE) == lib_mod.LBM_OK
+    assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_DEVICE
+    assert L.lbm_set_store_mode(h, 2) == lib_mod.LBM_ERR_ARG
+    assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_DEVICE
+    L.lbm_destroy(h)
+    rc, h = _create(runtime.params(lattice="D3Q19", nx=8, ny=8, nz=8))
+    assert rc == 0
+    assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_DEVICE) == lib_mod.LBM_ERR_UNSUPPORTED
+    assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_STREAMING) == lib_mod.LBM_OK
+    assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_STREAMING
+    L.lbm_destroy(h)
+    assert L.lbm_get_store_mode(None) == -1
+    assert L.lbm_set_store_mode(None, 0) == lib_mod.LBM_ERR_ARG

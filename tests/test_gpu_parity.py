@@ -273,11 +273,49 @@ def test_autotune_restores_state_and_skips_shapes_the_precision_lacks(prec):
     assert runtime._lib.lib().lbm_get_tile_shape(sim.h) == best
     if prec == "fp64":
         assert sim.tile_shape()[0] * sim.tile_shape()[1] <= 1024
+    assert sim.store_mode() in ("streaming", "device")
     assert sim.time == 4
     sim.step(5)
     assert torch.equal(sim.get_f(), ref.get_f())
     ref.close()
     sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_scope_stores_give_the_same_bits(prec):
+    """Both store modes of the D2Q9 step write the same values: a ragged periodic
+    lattice (partial tiles, improved scheme) and one with plates and the MRT
+    collision (standard scheme), through graph replays, odd and even step counts,
+    with the mode switched between calls."""
+    cases = [
+        (runtime.params("D2Q9", 70, 45, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec),
+         _droplet((45, 70), "vdW", 0.8, 12.0)),
+        (runtime.params("D2Q9", 64, 40, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec, scheme="standard",
+                        collision="mrt", tau_e=0.9, tau_s=1.1, tau_q=1.2, walls=(0.01, -0.01)),
+         _droplet((40, 64), "vdW", 0.8, 10.0)),
+    ]
+    for p, rho0 in cases:
+        print(f"case store modes {prec} {p.nx}x{p.ny} walls={p.walls}", flush=True)
+        a, b = runtime.LBM(p), runtime.LBM(p)
+        a.init(rho0)
+        b.init(rho0)
+        b.set_store_mode("device")
+        assert b.store_mode() == "device"
+        for n in (1, 26):
+            a.step(n)
+            b.step(n)
+            assert torch.equal(a.get_f(), b.get_f())
+        b.set_store_mode("streaming")
+        a.step(7)
+        b.step(7)
+        assert torch.equal(a.get_f(), b.get_f())
+        assert a.diagnostics() == b.diagnostics()
+        a.close()
+        b.close()
+    d3 = runtime.LBM(runtime.params("D3Q19", 8, 8, 8, T_over_Tc=0.8))
+    with pytest.raises(RuntimeError):
+        d3.set_store_mode("device")
+    d3.close()
 
 
 def test_state_round_trips_and_zero_steps():
