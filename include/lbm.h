@@ -300,21 +300,21 @@ int lbm_num_tile_shapes(const lbm_ctx* h);
 int lbm_describe_tile_shape(const lbm_ctx* h, int shape_index, int* bx, int* by, int* bz);
 int lbm_set_use_graphs(lbm_ctx* h, int on);
 
-/* How the D2Q9 step stores the new populations (Eq. 10's f*):
+/* How the step kernels store the new populations (Eq. 10's f*):
  *   LBM_STORES_STREAMING  non-temporal stores (default; the choice for lattices
  *                         streamed through HBM)
  *   LBM_STORES_DEVICE     device-scope stores, written through the L2 during the
  *                         kernel: nothing is left for the end-of-kernel
- *                         write-back, which pays when both state buffers stay in
- *                         the last-level cache between steps (e.g. 512^2 float64)
- * The results are identical.  D3Q19 offers streaming stores only (LBM_STORES_DEVICE
- * returns LBM_ERR_UNSUPPORTED).  A change drops the captured graphs.
+ *                         write-back, which pays when the state buffers stay
+ *                         (mostly) in the last-level cache between steps (e.g.
+ *                         D2Q9 512^2 float64, D3Q19 256 x 256 x 32 float32)
+ * The results are identical.  A change drops the captured graphs.
  * lbm_get_store_mode returns the mode, -1 for a null handle. */
 enum lbm_store_mode { LBM_STORES_STREAMING = 0, LBM_STORES_DEVICE = 1 };
 int lbm_set_store_mode(lbm_ctx* h, int mode);
 int lbm_get_store_mode(const lbm_ctx* h);
 
-/* Pick the fastest tile shape and (D2Q9) store mode by timing `steps` steps of
+/* Pick the fastest tile shape and store mode by timing `steps` steps of
  * each pair, twice, on the current state (the state, the time level and the
  * blow-up flags are restored afterwards); returns the chosen shape index and
  * leaves both selected. */

@@ -334,7 +334,7 @@ hipError_t launch_step(lbm_ctx* h, const StepArgs& a, int mode, hipStream_t s) {
         b.any_mrt |= R.mrt;
         b.any_plates |= R.walls;
     }
-    b.write_through = h->lattice == LBM_D2Q9 && h->store_mode == LBM_STORES_DEVICE;
+    b.write_through = h->store_mode == LBM_STORES_DEVICE;
     if (h->lattice == LBM_D2Q9 && h->params.size() == 1) {
         int bx, by;
         h->shape_dims(h->shape, bx, by);
@@ -768,8 +768,6 @@ int lbm_set_tile_shape(lbm_ctx* h, int s) {
 int lbm_set_store_mode(lbm_ctx* h, int mode) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (mode != LBM_STORES_STREAMING && mode != LBM_STORES_DEVICE) return fail(LBM_ERR_ARG, "bad store mode");
-    if (mode == LBM_STORES_DEVICE && h->lattice != LBM_D2Q9)
-        return fail(LBM_ERR_UNSUPPORTED, "device-scope population stores are implemented for D2Q9");
     if (mode != h->store_mode) {
         h->store_mode = mode;
         h->drop_graphs();             // the captured launches carry the old mode
@@ -802,7 +800,7 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     HIP_TRY(hipEventCreate(&e1));
     int best = h->shape, best_mode = h->store_mode;
     float best_ms = 1e30f;
-    const int modes = h->lattice == LBM_D2Q9 ? 2 : 1;
+    const int modes = 2;
     for (int s = 0; s < h->num_shapes() && rc == LBM_OK; ++s) {
         rc = lbm_set_tile_shape(h, s);
         if (rc == LBM_ERR_UNSUPPORTED) {       // a shape this lattice or precision does not offer

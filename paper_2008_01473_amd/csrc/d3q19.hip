@@ -459,8 +459,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 }
                 collide<T>(f, r, drho, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
                 if constexpr (F32) keep_mass_on_axes<19, 6, T>(f, m_in);
+                if (args.write_through) {
 #pragma unroll
-                for (int a = 0; a < 19; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
+                    for (int a = 0; a < 19; ++a) st_dev(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 19; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
+                }
             }
             acc.mass += F32 ? m_in : (double)drho;
             acc.mx += (double)(r * ux);

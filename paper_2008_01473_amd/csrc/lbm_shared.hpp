@@ -104,7 +104,7 @@ struct StepArgs {
     int nx0, ny0, slow_x0, slow_y0;
     int any_mrt;              // some lattice of the launch uses the MRT collision (D2Q9)
     int any_plates;           // some lattice of the launch has plates (D2Q9)
-    int write_through;        // D2Q9: store the populations at device scope (st_dev), not non-temporally
+    int write_through;        // store the populations at device scope (st_dev), not non-temporally
 };
 
 }  // namespace lbm

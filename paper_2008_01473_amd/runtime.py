@@ -175,7 +175,7 @@ class LBM:
     _STORES = {"streaming": _lib.LBM_STORES_STREAMING, "device": _lib.LBM_STORES_DEVICE}
 
     def set_store_mode(self, mode):
-        """"streaming" (non-temporal stores) or "device" (device-scope stores, D2Q9)."""
+        """"streaming" (non-temporal stores) or "device" (device-scope stores)."""
         check(_lib.lib().lbm_set_store_mode(self.h, self._STORES[mode]), "lbm_set_store_mode")
 
     def store_mode(self):

@@ -171,8 +171,9 @@ def test_adjoint_and_copy_entry_points_reject_before_touching_memory():
 
 
 def test_store_mode_selection_on_the_host():
-    """Streaming stores by default; device-scope stores are a D2Q9 option; bad
-    values are refused and leave the mode as it was (no GPU call involved)."""
+    """Streaming stores by default, device-scope stores on request, for both
+    lattices; bad values are refused and leave the mode as it was (no GPU call
+    involved)."""
     L = lib()
     rc, h = _create(runtime.params(nx=16, ny=16))
     assert rc == 0
@@ -184,7 +185,8 @@ def test_store_mode_selection_on_the_host():
     L.lbm_destroy(h)
     rc, h = _create(runtime.params(lattice="D3Q19", nx=8, ny=8, nz=8))
     assert rc == 0
-    assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_DEVICE) == lib_mod.LBM_ERR_UNSUPPORTED
+    assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_DEVICE) == lib_mod.LBM_OK
+    assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_DEVICE
     assert L.lbm_set_store_mode(h, lib_mod.LBM_STORES_STREAMING) == lib_mod.LBM_OK
     assert L.lbm_get_store_mode(h) == lib_mod.LBM_STORES_STREAMING
     L.lbm_destroy(h)

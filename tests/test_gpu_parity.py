@@ -283,10 +283,10 @@ def test_autotune_restores_state_and_skips_shapes_the_precision_lacks(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_device_scope_stores_give_the_same_bits(prec):
-    """Both store modes of the D2Q9 step write the same values: a ragged periodic
-    lattice (partial tiles, improved scheme) and one with plates and the MRT
-    collision (standard scheme), through graph replays, odd and even step counts,
-    with the mode switched between calls."""
+    """Both store modes write the same values: D2Q9 on a ragged periodic lattice
+    (partial tiles, improved scheme) and one with plates and the MRT collision
+    (standard scheme), through graph replays, odd and even step counts, with the
+    mode switched between calls; D3Q19 on a ragged lattice."""
     cases = [
         (runtime.params("D2Q9", 70, 45, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec),
          _droplet((45, 70), "vdW", 0.8, 12.0)),
@@ -312,10 +312,21 @@ def test_device_scope_stores_give_the_same_bits(prec):
         assert a.diagnostics() == b.diagnostics()
         a.close()
         b.close()
-    d3 = runtime.LBM(runtime.params("D3Q19", 8, 8, 8, T_over_Tc=0.8))
-    with pytest.raises(RuntimeError):
-        d3.set_store_mode("device")
-    d3.close()
+    # D3Q19: a ragged lattice in float32 (z-chunked sweep with partial chunks)
+    p3 = runtime.params("D3Q19", 20, 18, 37, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec)
+    m = _maxwell("vdW", 0.8)
+    r3 = inputs.droplet((37, 18, 20), m["rho_g"], m["rho_l"], 6.0, 3.0, noise=1e-4, seed=2)
+    print(f"case store modes D3Q19 {prec} 20x18x37", flush=True)
+    a, b = runtime.LBM(p3), runtime.LBM(p3)
+    a.init(r3)
+    b.init(r3)
+    b.set_store_mode("device")
+    for n in (1, 12):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.get_f(), b.get_f())
+    a.close()
+    b.close()
 
 
 def test_state_round_trips_and_zero_steps():
