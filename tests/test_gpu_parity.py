@@ -408,13 +408,19 @@ def test_fp32_deviation_storage_tracks_fp64(lattice, scheme):
     sim.close()
 
 
-def test_full_size_512sq_cs_droplet_one_step():
+@pytest.mark.parametrize("stores", ["device", "streaming"])
+def test_full_size_512sq_cs_droplet_one_step(stores):
     """The 512 x 512 Carnahan-Starling droplet (r = 80, T/Tc = 0.8, kappa = 0.01,
-    tau = 0.8) in the launch configuration the benchmark times: whole-lattice
+    tau = 0.8) in the launch configuration the benchmark times (32 x 16 tiles,
+    device-scope stores, the tuner's pick) and with streaming stores: whole-lattice
     parity after one step and after two graph-replayed steps."""
     p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8)
     rho0 = _droplet((512, 512), "CS", 0.8, 80.0)
     sim = runtime.LBM(p)
+    sim.set_tile_shape(0)
+    assert sim.tile_shape() == (32, 16, 1)
+    sim.set_store_mode(stores)
+    print(f"case 512^2 full size, {stores} stores", flush=True)
     sim.init(rho0)
     refs = oracle_run(p, rho0, [1, 3])
     sim.step(1)
