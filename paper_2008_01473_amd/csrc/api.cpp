@@ -85,7 +85,7 @@ struct lbm_ctx {
     std::vector<LatticeRec> recs;
     std::vector<Tile> tiles;
     int shape = 0;
-    int store_mode = LBM_STORES_STREAMING;   // D2Q9 population stores (lbm_set_store_mode)
+    int store_mode = LBM_STORES_STREAMING;   // how the step kernels store f* (lbm_set_store_mode)
     long long field_total = 0, state_nodes = 0;
     size_t state_bytes = 0, ws_bytes = 0;
     size_t off_recs = 0, off_tiles = 0, off_partial = 0, off_status = 0, off_diag = 0;
@@ -800,14 +800,15 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
     HIP_TRY(hipEventCreate(&e1));
     int best = h->shape, best_mode = h->store_mode;
     float best_ms = 1e30f;
-    const int modes = 2;
+    const int modes[2] = {LBM_STORES_STREAMING, LBM_STORES_DEVICE};
     for (int s = 0; s < h->num_shapes() && rc == LBM_OK; ++s) {
         rc = lbm_set_tile_shape(h, s);
         if (rc == LBM_ERR_UNSUPPORTED) {       // a shape this lattice or precision does not offer
             rc = LBM_OK;
             continue;
         }
-        for (int m = 0; m < modes && rc == LBM_OK; ++m) {
+        for (const int m : modes) {
+            if (rc != LBM_OK) break;
             rc = lbm_set_store_mode(h, m);
             if (rc != LBM_OK) break;
             float ms_min = 1e30f;
