@@ -1,5 +1,5 @@
-"""bench.py's output contract: one JSON line on stdout with the fields a benchmark
-driver reads (metric, value and unit; the step count and time; the workload; the
+"""bench.py's output contract: one JSON line on stdout with the fields its readers
+rely on (metric, value and unit; the step count and time; the workload; the
 roofline object of the timed kernel; the CPU baseline of the oracle).  The refusal
 of several GPUs runs on the CPU; the JSON line itself needs a GPU."""
 
