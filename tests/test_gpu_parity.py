@@ -286,7 +286,8 @@ def test_device_scope_stores_give_the_same_bits(prec):
     """Both store modes write the same values: D2Q9 on a ragged periodic lattice
     (partial tiles, improved scheme) and one with plates and the MRT collision
     (standard scheme), through graph replays, odd and even step counts, with the
-    mode switched between calls; D3Q19 on a ragged lattice."""
+    mode switched between calls; a batch of two D2Q9 lattices; D3Q19 on a ragged
+    lattice."""
     cases = [
         (runtime.params("D2Q9", 70, 45, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec),
          _droplet((45, 70), "vdW", 0.8, 12.0)),
@@ -312,6 +313,22 @@ def test_device_scope_stores_give_the_same_bits(prec):
         assert a.diagnostics() == b.diagnostics()
         a.close()
         b.close()
+    # a batch: tiles that take their lattice's addressing from the tile records
+    pb = [runtime.params("D2Q9", 48, 40, 1, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec),
+          runtime.params("D2Q9", 70, 33, 1, T_over_Tc=0.85, kappa=0.015, tau=0.9, precision=prec)]
+    rb = np.concatenate([_droplet((40, 48), "vdW", 0.8, 9.0).ravel(), _droplet((33, 70), "vdW", 0.85, 8.0).ravel()])
+    print(f"case store modes batch {prec}", flush=True)
+    a, b = runtime.LBM(pb), runtime.LBM(pb)
+    a.init(rb)
+    b.init(rb)
+    b.set_store_mode("device")
+    for n in (1, 14):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.get_f(), b.get_f())
+    assert a.diagnostics() == b.diagnostics()
+    a.close()
+    b.close()
     # D3Q19: a ragged lattice in float32 (z-chunked sweep with partial chunks)
     p3 = runtime.params("D3Q19", 20, 18, 37, T_over_Tc=0.8, kappa=0.02, tau=0.8, precision=prec)
     m = _maxwell("vdW", 0.8)
