@@ -161,7 +161,13 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Create a handle for one lattice.  Checks the parameters, solves the Maxwell
  * construction on the host (for the FP32_DEV defaults) and plans the tiling.
- * No device memory is allocated.  *out receives the handle. */
+ * No device memory is allocated.  *out receives the handle.
+ * The parameters are those of the paper's experiments (Sec. IV A: the van der
+ * Waals free energy of Eq. 30 with a, b, R, the temperature as T/T_c, kappa of
+ * Eq. 1 and the relaxation rates of Eq. 8); T_c = 8a/(27Rb) for vdW (Sec. IV A).
+ * Errors: LBM_ERR_ARG for an invalid parameter (the message names it),
+ * LBM_ERR_UNSUPPORTED for a valid combination the library does not implement
+ * (e.g. MRT or plates on D3Q19, or more than 2^31 populations in one lattice). */
 int lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
 
 /* Create a handle for `count` independent lattices advanced together by one
@@ -276,8 +282,13 @@ int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m,
 int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double* grad_rho0, void* ws,
                      double* grad);
 
-/* Maxwell construction (equal mu_EOS and p_EOS) of the chosen EOS at T/T_c, on
- * the host in float64.  Returns LBM_ERR_DOMAIN when there is no coexistence. */
+/* Maxwell construction of the chosen EOS at T/T_c, on the host in float64: the
+ * gas and liquid densities with equal bulk chemical potential (Eq. 2 without the
+ * gradient term) and equal bulk pressure (Eq. 3), which are the analytical
+ * coexistence densities of Sec. IV A and Table II and the uniform mu of Appendix
+ * A.  Outputs are host pointers (none may be NULL).  Returns LBM_ERR_ARG for
+ * non-positive constants or T/T_c, LBM_ERR_DOMAIN when there is no coexistence
+ * (T/T_c >= 1). */
 int lbm_maxwell(int eos, double a, double b, double R, double T_over_Tc,
                 double* rho_g, double* rho_l, double* mu_sat, double* p_sat);
 
@@ -299,6 +310,15 @@ int lbm_get_tile_shape(const lbm_ctx* h);
 int lbm_num_tile_shapes(const lbm_ctx* h);
 int lbm_describe_tile_shape(const lbm_ctx* h, int shape_index, int* bx, int* by, int* bz);
 int lbm_set_use_graphs(lbm_ctx* h, int on);
+
+/* D3Q19 z-chunk length: bz = 0 (default) takes it from the tuning index (chunks
+ * aimed at a work-group count); bz >= 16 fixes the number of z-slices each work
+ * group sweeps for every tile shape (the last chunk of a lattice may be shorter).
+ * D2Q9 handles accept only 0.  Re-plans like lbm_set_tile_shape (synchronises
+ * the stream, drops captured graphs).  LBM_ERR_ARG for 0 < bz < 16.
+ * lbm_get_zchunk returns the fixed length, 0 when automatic, -1 for a null handle. */
+int lbm_set_zchunk(lbm_ctx* h, int bz);
+int lbm_get_zchunk(const lbm_ctx* h);
 
 /* How the step kernels store the new populations (Eq. 10's f*):
  *   LBM_STORES_STREAMING  non-temporal stores (default; the choice for lattices

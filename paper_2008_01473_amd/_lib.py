@@ -73,6 +73,8 @@ SIGNATURES = {
     "lbm_num_tile_shapes": (c_int, [c_void_p]),
     "lbm_describe_tile_shape": (c_int, [c_void_p, c_int, P(c_int), P(c_int), P(c_int)]),
     "lbm_set_use_graphs": (c_int, [c_void_p, c_int]),
+    "lbm_set_zchunk": (c_int, [c_void_p, c_int]),
+    "lbm_get_zchunk": (c_int, [c_void_p]),
     "lbm_set_store_mode": (c_int, [c_void_p, c_int]),
     "lbm_get_store_mode": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p, c_int, c_void_p]),

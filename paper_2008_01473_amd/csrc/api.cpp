@@ -74,6 +74,7 @@ constexpr int kGraphChunk = 256;   // even, so replaying a chunk keeps the buffe
 // chunks re-read fewer warm-up slices; more chunks fill the CUs better.
 constexpr int kNumZTargets = 3;
 constexpr long long kZTargets[kNumZTargets] = {512, 1024, 256};
+constexpr int kMinZChunk = 16;     // shortest z-chunk lbm_set_zchunk accepts (below: mostly warm-up)
 
 }  // namespace
 
@@ -85,6 +86,7 @@ struct lbm_ctx {
     std::vector<LatticeRec> recs;
     std::vector<Tile> tiles;
     int shape = 0;
+    int zchunk_fixed = 0;     // D3Q19: z-chunk length set by lbm_set_zchunk (0: from the tuning index)
     int store_mode = LBM_STORES_STREAMING;   // how the step kernels store f* (lbm_set_store_mode)
     long long field_total = 0, state_nodes = 0;
     size_t state_bytes = 0, ws_bytes = 0;
@@ -144,6 +146,7 @@ static int band_width(int ntx, int bx) { return std::max(1, std::min(ntx, 512 / 
 
 int lbm_ctx::zchunk_for(int s) const {
     if (lattice == LBM_D2Q9) return 1;
+    if (zchunk_fixed > 0) return zchunk_fixed;
     int bx, by;
     shape_dims(s, bx, by);
     long long cols = 0;
@@ -486,10 +489,17 @@ int lbm_create_batch(const lbm_params* p, int count, void* hip_stream, lbm_ctx**
     h->state_nodes = soff;
     const size_t word = h->precision == LBM_FP64 ? 8 : 4;
     h->state_bytes = align256((size_t)soff * h->Q * word);
-    // the largest tile list over all shapes, so that re-tiling fits the workspace
+    // the largest tile list over all shapes, so that re-tiling fits the workspace;
+    // for D3Q19 also with the shortest z-chunk lbm_set_zchunk accepts
     for (int s = 0; s < h->num_shapes(); ++s) {
         std::vector<LatticeRec> rr = h->recs;
         h->max_tiles = std::max<int>(h->max_tiles, (int)h->plan(s, rr).size());
+        if (h->lattice == LBM_D3Q19) {
+            h->zchunk_fixed = kMinZChunk;
+            rr = h->recs;
+            h->max_tiles = std::max<int>(h->max_tiles, (int)h->plan(s, rr).size());
+            h->zchunk_fixed = 0;
+        }
     }
     h->shape = 0;
     h->tiles = h->plan(h->shape, h->recs);
@@ -765,6 +775,19 @@ int lbm_set_tile_shape(lbm_ctx* h, int s) {
     return LBM_OK;
 }
 
+int lbm_set_zchunk(lbm_ctx* h, int bz) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->lattice != LBM_D3Q19) return bz == 0 ? LBM_OK : fail(LBM_ERR_UNSUPPORTED, "z-chunks are D3Q19 only");
+    if (bz != 0 && bz < kMinZChunk) return fail(LBM_ERR_ARG, "a fixed z-chunk must be 0 (automatic) or >= 16");
+    const int old = h->zchunk_fixed;
+    h->zchunk_fixed = bz;
+    const int rc = lbm_set_tile_shape(h, h->shape);      // re-plan with the new chunk length
+    if (rc != LBM_OK) h->zchunk_fixed = old;
+    return rc;
+}
+
+int lbm_get_zchunk(const lbm_ctx* h) { return h ? h->zchunk_fixed : -1; }
+
 int lbm_set_store_mode(lbm_ctx* h, int mode) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (mode != LBM_STORES_STREAMING && mode != LBM_STORES_DEVICE) return fail(LBM_ERR_ARG, "bad store mode");
@@ -826,6 +849,11 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
                 h->cur = cur0;
                 HIP_TRY(hipMemcpyAsync(h->buf[h->cur], scratch, h->state_bytes, hipMemcpyDeviceToDevice,
                                        h->stream));
+                // every trial starts from the same flags, so a lattice flagged in
+                // one trial is not skipped (less work) in the next
+                HIP_TRY(hipMemcpyAsync(h->d_status(), st0.data(), st0.size() * sizeof(unsigned),
+                                       hipMemcpyHostToDevice, h->stream));
+                HIP_TRY(hipStreamSynchronize(h->stream));
                 h->t = t0;
             }
             if (rc == LBM_OK && ms_min < best_ms) {
@@ -859,6 +887,9 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
     LatticeRec& R = h->recs[i];
     R.kappa = kappa;
     R.RT = p.R * T_over_Tc * host::critical_temperature(p.eos, p.a, p.b, p.R);
+    // The adjoint kernels take the lattice record by value, so captured segment
+    // graphs hold the old kappa and RT: drop every captured graph.
+    h->drop_graphs();
     if (h->bound) {
         HIP_TRY(hipStreamSynchronize(h->stream));
         return upload_tables(h);

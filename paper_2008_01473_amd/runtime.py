@@ -169,6 +169,10 @@ class LBM:
         check(L.lbm_describe_tile_shape(self.h, s, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)))
         return bx.value, by.value, bz.value
 
+    def set_zchunk(self, bz):
+        """D3Q19: fix the z-chunk each work group sweeps (>= 16), or 0 for automatic."""
+        check(_lib.lib().lbm_set_zchunk(self.h, int(bz)), "lbm_set_zchunk")
+
     def use_graphs(self, on=True):
         check(_lib.lib().lbm_set_use_graphs(self.h, 1 if on else 0))
 

@@ -192,3 +192,29 @@ def test_store_mode_selection_on_the_host():
     L.lbm_destroy(h)
     assert L.lbm_get_store_mode(None) == -1
     assert L.lbm_set_store_mode(None, 0) == lib_mod.LBM_ERR_ARG
+
+
+def test_fixed_z_chunk_on_the_host():
+    """lbm_set_zchunk: D3Q19 takes 0 or >= 16 slices and reports it through the tile
+    description (a plan that needs no device memory while unbound); D2Q9 takes only 0."""
+    L = lib()
+    rc, h = _create(runtime.params(lattice="D3Q19", nx=70, ny=12, nz=260))
+    assert rc == 0
+    assert L.lbm_get_zchunk(h) == 0
+    shape = 3 * 3        # 64 x 4 tiles, first z-chunk target
+    assert L.lbm_set_tile_shape(h, shape) == lib_mod.LBM_OK
+    assert L.lbm_set_zchunk(h, 128) == lib_mod.LBM_OK
+    bx, by, bz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.lbm_describe_tile_shape(h, shape, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert (bx.value, by.value, bz.value) == (64, 4, 128)
+    assert L.lbm_get_zchunk(h) == 128
+    assert L.lbm_set_zchunk(h, 8) == lib_mod.LBM_ERR_ARG
+    assert L.lbm_get_zchunk(h) == 128
+    assert L.lbm_set_zchunk(h, 16) == lib_mod.LBM_OK       # the shortest: its plan fits the workspace
+    assert L.lbm_set_zchunk(h, 0) == lib_mod.LBM_OK
+    L.lbm_destroy(h)
+    rc, h = _create(runtime.params(nx=16, ny=16))
+    assert L.lbm_set_zchunk(h, 0) == lib_mod.LBM_OK
+    assert L.lbm_set_zchunk(h, 32) == lib_mod.LBM_ERR_UNSUPPORTED
+    L.lbm_destroy(h)
+    assert L.lbm_get_zchunk(None) == -1

@@ -111,8 +111,9 @@ def test_rollout_gradients_match_oracle_autograd(scheme):
 
 def test_rollout_gradients_match_central_differences():
     """Improved scheme, 40 steps: the adjoint gradients against central finite
-    differences (h = 1e-6) of the GPU float64 forward, for kappa, T/Tc and one
-    random direction in rho0."""
+    differences (h = 1e-6) of the GPU float64 forward, for kappa, T/Tc, eight
+    seeded components of rho0 (two of them in the interface) and one random
+    direction in rho0."""
     p, rho0 = _case("improved", n=(32, 32))
     n_steps = 40
     target = torch.as_tensor(rho0).reshape(-1).cuda() * 1.01
@@ -139,7 +140,57 @@ def test_rollout_gradients_match_central_differences():
     assert float(kd.grad) == pytest.approx(fd_k, rel=1e-5)
     assert float(td.grad) == pytest.approx(fd_t, rel=1e-5)
     assert ad_v == pytest.approx(fd_v, rel=1e-5)
+    # eight seeded components of rho0: six drawn uniformly, two on the interface
+    # ring (where the gradient is largest and least linear)
+    n = base.numel()
+    comps = [int(i) for i in np.random.default_rng(7).choice(n, 6, replace=False)]
+    yy, xx = np.divmod(np.arange(n), 32)
+    ring = np.flatnonzero(np.abs(np.hypot(xx - 16.0, yy - 16.0) - 5.0) < 0.5)
+    comps += [int(i) for i in np.random.default_rng(8).choice(ring, 2, replace=False)]
+    g_r0 = r0d.grad.detach().cpu()
+    for i in comps:
+        e = torch.zeros(n, dtype=torch.float64, device="cuda")
+        e[i] = 1.0
+        fd_i = (loss_at(base + h * e, 0.02, 0.8) - loss_at(base - h * e, 0.02, 0.8)) / (2 * h)
+        print(f"FD: rho0[{i}] {fd_i:.8e} vs {float(g_r0[i]):.8e}", flush=True)
+        # absolute floor: components far from the droplet carry tiny gradients whose
+        # central difference is limited by the loss's rounding (~1e-16 L / h)
+        assert float(g_r0[i]) == pytest.approx(fd_i, rel=1e-5, abs=1e-7)
     roll.close()
+
+
+def test_second_backward_after_a_physics_change():
+    """One Rollout runs forward and backward at kappa = 0.02, then forward and
+    backward at kappa = 0.025, T/Tc = 0.82 on the same buffers (segment graphs
+    on): the second gradients equal, bit for bit, those of a fresh Rollout at the
+    new parameters."""
+    p, rho0 = _case("improved", n=(24, 28))
+    n_steps = 24
+    target = torch.as_tensor(rho0).reshape(-1).cuda() * 1.01
+
+    def grads(roll, k, t):
+        r0 = torch.as_tensor(rho0).reshape(-1).cuda().requires_grad_(True)
+        kd = torch.tensor(k, dtype=torch.float64, device="cuda", requires_grad=True)
+        td = torch.tensor(t, dtype=torch.float64, device="cuda", requires_grad=True)
+        rho_n, u_n = rollout(r0, kd, td, roll, n_steps)
+        (((rho_n - target) ** 2).sum() + (u_n ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        return r0.grad.clone(), kd.grad.clone(), td.grad.clone()
+
+    roll = Rollout(p)
+    roll.sim.use_graphs(True)
+    g_first = grads(roll, 0.02, 0.8)
+    g_second = grads(roll, 0.025, 0.82)
+    roll.close()
+    fresh = Rollout(p)
+    fresh.sim.use_graphs(True)
+    g_fresh = grads(fresh, 0.025, 0.82)
+    fresh.close()
+    print(f"second backward: dkappa {float(g_second[1]):.10e} fresh {float(g_fresh[1]):.10e} "
+          f"first {float(g_first[1]):.10e}", flush=True)
+    assert not torch.equal(g_first[1], g_second[1])
+    for a, b in zip(g_second, g_fresh):
+        assert torch.equal(a, b)
 
 
 def test_adjoint_dot_product_identity():

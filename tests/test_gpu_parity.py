@@ -1,7 +1,7 @@
 """GPU path vs the CPU oracle, element by element, through the C ABI.
 
-Float64 bar: relative error per field <= 1e-12 (populations, rho, u with a 1e-8
-floor, mu).  Inputs are the seeded synthetic fields of paper_2008_01473_amd.inputs,
+Float64 bar: relative error per field <= 1e-12 (populations, rho, u with a 1e-2
+floor, mu with a 1e-3 floor; the floors are explained in parity_util).  Inputs are the seeded synthetic fields of paper_2008_01473_amd.inputs,
 shared by both sides; the coexistence densities come from the oracle's Maxwell
 construction."""
 
@@ -474,42 +474,93 @@ def test_full_size_512sq_cs_droplet_one_step(stores):
     sim.close()
 
 
-def _window_oracle(p, rho0, center, radius, steps):
-    """Oracle on a periodic window of the initial field around `center`; the central
-    node is exact for `steps` steps when radius >= 5 * steps + 1."""
-    shape = shape_of(p)
-    idx = [np.arange(c - radius, c + radius + 1) % n for c, n in zip(center, shape)]
-    sub = rho0[np.ix_(*idx)]
-    prm = oracle_params(p)
-    f = model.run(model.init(torch.as_tensor(sub), prm), prm, steps)
-    return f[(slice(None),) + (radius,) * len(shape)], model.fields(f, prm)
+BENCH_D3Q19_TILE = 3 * 3          # tuning index of the 64 x 4 column (first z-chunk target)
 
 
-def test_full_size_256cube_d3q19_sampled_nodes():
-    """The 256^3 D3Q19 vdW droplet (r = 40, T/Tc = 0.7, kappa = 0.02, tau = 1.0, FP32
-    deviation storage) in the benchmark's launch configuration: one step, sampled
-    nodes against oracle windows, and exact mass conservation in the FP64 sums."""
-    p = runtime.params("D3Q19", 256, 256, 256, eos="vdW", T_over_Tc=0.7, kappa=0.02, tau=1.0, precision="fp32")
-    rho0 = _droplet((256, 256, 256), "vdW", 0.7, 40.0)
+def _bench_d3q19_config(sim, zchunk=128):
+    """The launch configuration the benchmark times for the 256^3 sweep: 64 x 4
+    columns, 128-slice z-chunks, streaming stores."""
+    sim.set_tile_shape(BENCH_D3Q19_TILE)
+    sim.set_zchunk(zchunk)
+    sim.set_store_mode("streaming")
+    assert sim.tile_shape() == (64, 4, zchunk)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_d3q19_in_the_benchmark_tile_and_chunk(prec):
+    """70 x 12 x 260 in the 256^3 benchmark's configuration (64 x 4 columns: two in x,
+    the second ragged; three in y; 128-slice z-chunks: two full, one of 4 slices;
+    streaming stores), improved scheme, vdW T/Tc = 0.85: whole-field parity after
+    1 and 3 steps, at 1e-12 in float64 and at float32 round-off (2e-6) for the
+    deviation storage, whose register FIFO path is the benchmarked one."""
+    p = runtime.params("D3Q19", 70, 12, 260, eos="vdW", T_over_Tc=0.85, kappa=0.02, tau=1.0, precision=prec)
+    rho0 = _droplet((260, 12, 70), "vdW", 0.85, 5.0)
     sim = runtime.LBM(p)
+    _bench_d3q19_config(sim)
+    print(f"case D3Q19 {prec} 70x12x260, 64x4 tiles, 128-slice chunks", flush=True)
+    sim.init(rho0)
+    refs = oracle_run(p, rho0, [1, 3])
+    t = 0
+    for s in (1, 3):
+        sim.step(s - t)
+        t = s
+        if prec == "fp64":
+            print(compare(sim, p, refs[s]), flush=True)
+        else:
+            f_ref, fl = refs[s]
+            f = sim.get_f().reshape((19, 260, 12, 70))
+            rho, u, mu = sim.moments()
+            errs = {"f": rel_err(f, f_ref), "rho": rel_err(rho.reshape(260, 12, 70), fl["rho"]),
+                    "u_abs": float((u.reshape(3, 260, 12, 70).cpu() - fl["u"]).abs().max()),
+                    "mu_abs": float((mu.reshape(260, 12, 70).cpu() - fl["mu"]).abs().max())}
+            print(f"fp32 step {s}: {errs}", flush=True)
+            assert errs["f"] < 2e-6 and errs["rho"] < 2e-6 and errs["u_abs"] < 2e-6 and errs["mu_abs"] < 2e-6
+    sim.close()
+
+
+def test_full_size_256cube_d3q19_z_slab_windows():
+    """The 256^3 D3Q19 vdW droplet (r = 40, kappa = 0.02, tau = 1.0, float32 deviation
+    storage) at T/Tc = 0.85, the benchmark's temperature, in its launch configuration
+    (64 x 4 columns, 128-slice z-chunks, streaming stores): after one step, whole
+    z-slabs of 8 slices (all 256 x 256 nodes each) against the oracle run on the slab
+    plus 8 slices on either side (periodic in x and y like the lattice; the populations
+    after one step depend on the state within 4 nodes, the fields within 7).  The slabs
+    cross the droplet's centre at the seam of the two z-chunks (z = 124..131), its lower
+    interface (z = 84..91) and the periodic wrap (z = 252..259 mod 256); the FP64 mass
+    sum is the initial mass."""
+    n = 256
+    p = runtime.params("D3Q19", n, n, n, eos="vdW", T_over_Tc=0.85, kappa=0.02, tau=1.0, precision="fp32")
+    rho0 = _droplet((n, n, n), "vdW", 0.85, 40.0)
+    sim = runtime.LBM(p)
+    _bench_d3q19_config(sim)
     sim.init(rho0)
     sim.step(1)
-    f = sim.get_f()
-    rng = np.random.default_rng(7)
-    samples = [(128, 128, 88), (128, 168, 128), (0, 0, 0), (255, 17, 128)] + \
-        [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(4)]
-    fmax = 0.0
-    worst = 0.0
-    for c in samples:
-        fr, _ = _window_oracle(p, rho0, c, 7, 1)
-        node = (c[0] * 256 + c[1]) * 256 + c[2]
-        g = f[:, node].cpu()
-        worst = max(worst, float((g - fr).abs().max()))
-        fmax = max(fmax, float(fr.abs().max()))
-    assert worst / fmax < 2e-6, worst / fmax
-    sim.step(1)
-    rho, _, _ = sim.moments()
+    f = sim.get_f().view(19, n, n, n)
+    rho, u, mu = sim.moments()
+    rho, u, mu = rho.view(n, n, n), u.view(3, n, n, n), mu.view(n, n, n)
+    prm = oracle_params(p)
+    margin = 8
+    f_scale = rho_scale = None
+    for z0 in (124, 84, 252):
+        zs = np.arange(z0 - margin, z0 + 8 + margin) % n
+        fr = model.run(model.init(torch.as_tensor(rho0[zs]), prm), prm, 1)
+        fl = model.fields(fr, prm)
+        win = torch.as_tensor(zs[margin:margin + 8]).cuda()
+        inner = slice(margin, margin + 8)
+        if f_scale is None:        # the slab through the droplet's centre holds the lattice's largest values
+            f_scale, rho_scale = float(fr[:, inner].abs().max()), float(fl["rho"][inner].abs().max())
+        # errors relative to the lattice's largest population and density, as in the
+        # whole-lattice float32 tests (float32 rounds deviations from one reference
+        # state, so its error is absolute, the same in gas and liquid)
+        ef = float((f.index_select(1, win).cpu() - fr[:, inner]).abs().max()) / f_scale
+        er = float((rho.index_select(0, win).cpu() - fl["rho"][inner]).abs().max()) / rho_scale
+        eu = float((u.index_select(1, win).cpu() - fl["u"][:, inner]).abs().max())
+        em = float((mu.index_select(0, win).cpu() - fl["mu"][inner]).abs().max())
+        print(f"case 256^3 slab z={z0}..{z0 + 7}: f {ef:.2e} rho {er:.2e} u_abs {eu:.2e} mu_abs {em:.2e}",
+              flush=True)
+        assert ef < 2e-6 and er < 2e-6 and eu < 2e-6 and em < 2e-6
     d = sim.diagnostics()[0]
+    assert d["status"] == 0
     assert d["mass"] == pytest.approx(float(rho0.sum()), rel=1e-6)
     sim.close()
 
