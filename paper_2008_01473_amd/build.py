@@ -26,6 +26,9 @@ COMMON_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one expression, so that every tile shape
+    # (each its own instantiation) rounds a node's arithmetic the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-variable", "-Wno-unused-function",
 ]
 

@@ -259,6 +259,25 @@ int check_params(const lbm_params& p) {
     return LBM_OK;
 }
 
+// Constants of the float32 chemical potential in deviation form (MuRef in the
+// kernels): mu_EOS(rho_ref + x) - mu_ref = k0 + RT [ln(rho q) + b x q q0] - 2 a x
+// (vdW, q = 1/(1 - b rho)) or k0 + RT [ln rho + g(h) - g(h0)] - 2 a x (CS).
+void set_dev_constants(LatticeRec& R, double Rgas) {
+    if (!(R.rho_ref > 0)) {
+        R.dev_q0 = R.dev_k0 = 0.0;
+        return;
+    }
+    const double T = R.RT / Rgas;
+    const double mu0 = host::mu_eos(R.eos, R.a, R.b, Rgas, T, R.rho_ref) - R.mu_ref;
+    if (R.eos == LBM_EOS_VDW) {
+        R.dev_q0 = 1.0 / (1.0 - R.b * R.rho_ref);
+        R.dev_k0 = mu0 - R.RT * std::log(R.rho_ref * R.dev_q0);
+    } else {
+        R.dev_q0 = 1.0 / (1.0 - 0.25 * R.b * R.rho_ref);
+        R.dev_k0 = mu0 - R.RT * std::log(R.rho_ref);
+    }
+}
+
 LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     LatticeRec R;
     std::memset(&R, 0, sizeof(R));
@@ -312,6 +331,7 @@ LatticeRec make_rec(const lbm_params& p, int variant, int Q) {
     R.pm_ref = pm_ref;
     R.mu_ref = 3.0 * pm_ref - R.c0;
     if (variant != kImproved) R.pm_ref = rho_ref / 3.0;
+    set_dev_constants(R, p.R);
     const double pmr = R.pm_ref;
     if (Q == 9) {
         R.fbar[0] = rho_ref - 5.0 * pmr / 3.0;
@@ -887,6 +907,7 @@ int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
     LatticeRec& R = h->recs[i];
     R.kappa = kappa;
     R.RT = p.R * T_over_Tc * host::critical_temperature(p.eos, p.a, p.b, p.R);
+    set_dev_constants(R, p.R);
     // The adjoint kernels take the lattice record by value, so captured segment
     // graphs hold the old kappa and RT: drop every captured graph.
     h->drop_graphs();

@@ -67,10 +67,15 @@ __device__ __forceinline__ void pull_plates(const S* const (&p)[9], int nx, int 
     }
 }
 
+// Sum of the moving populations, then the density deviation: the rest
+// population (the large deviation in float32 storage) is added last, so that the
+// sum is rounded once at its magnitude.
 template <typename T>
-__device__ __forceinline__ T sum9(const T f[9]) {
-    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+__device__ __forceinline__ T moving9(const T f[9]) {
+    return ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
 }
+template <typename T>
+__device__ __forceinline__ T sum9(const T f[9]) { return f[0] + moving9(f); }
 template <typename T>
 __device__ __forceinline__ T jx9(const T f[9]) { return (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]); }
 template <typename T>
@@ -100,14 +105,15 @@ __device__ __forceinline__ T ddy(const T* s, int c) {
 // BGK collision with Guo forcing (Eq. 14) and, for the improved scheme, the
 // correction term C of Eqs. 28-29 in population form; f holds the incoming
 // populations minus fbar and receives f* minus fbar.
-//   drho = rho - rho_ref, dpm = p_m - pm_ref (standard: drho / 3),
+//   drho = rho - rho_ref, Sm = the moving populations' sum (drho - f[0]),
+//   dpm = p_m - pm_ref (standard: drho / 3),
 //   php = p_m - rho/3 (zero in the standard scheme), Cxx = 3 d_x, Cyy = 3 d_y.
 // Equilibrium minus reference (M^-1 of Eq. 27 / Eq. 11):
 //   rest: drho - 5 dpm / 3 - (2/3) rho u^2
 //   axis: dpm / 3  + rho/9  (3 eu + 4.5 eu^2 - 1.5 u^2) - php eu / 2
 //   diag: dpm / 12 + rho/36 (3 eu + 4.5 eu^2 - 1.5 u^2) + php eu / 4
 template <typename T>
-__device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
+__device__ __forceinline__ void collide(T f[9], T rho, T Sm, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
                                         T Cyy, T omega) {
     const T usq = ux * ux + uy * uy;
     const T uF = ux * Fx + uy * Fy;
@@ -117,9 +123,10 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
     const T Cb = (Cyy - T(2) * Cxx) * T(1.0 / 6.0);   // +-y
     const T Cd = (Cxx + Cyy) * T(1.0 / 6.0);          // diagonals
     {
-        const T feq = drho - T(5.0 / 3.0) * dpm - T(2.0 / 3.0) * rho * usq;
+        // f0* = f0 + omega (feq0 - f0) + om2 (G0 + C0), feq0 - f0 = Sm - 5 dpm / 3 - (2/3) rho u^2
+        const T dfeq = Sm - T(5.0 / 3.0) * dpm - T(2.0 / 3.0) * rho * usq;
         const T G = T(4.0 / 9.0) * (T(-3) * uF);
-        f[0] = om1 * f[0] + omega * feq + om2 * (G - T(2) * Cd);
+        f[0] += (omega * dfeq + om2 * (G - T(2) * Cd));
     }
     // axis pairs: w = 1/9, php coefficient -1/2;  diagonal pairs: w = 1/36, +1/4
     const T Ua = dpm * T(1.0 / 3.0) - T(1.5) * r9 * usq;
@@ -141,7 +148,9 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
 // with rows  e: -4 + 3|e|^2,  eps: 4 - 21|e|^2/2 + 9|e|^4/2,  q_i: (-5 + 3|e|^2) e_i,
 // p_xx: e_x^2 - e_y^2,  p_xy: e_x e_y.  f holds populations minus fbar; the
 // non-equilibrium moments are formed from drho = rho - rho_ref and
-// dpm = p_m - pm_ref so that fbar's moments cancel:
+// dpm = p_m - pm_ref so that fbar's moments cancel; with ax, dg the sums of the
+// axis and diagonal populations, e(f) + 4 drho = 3 ax + 6 dg and
+// eps(f) - 4 drho = -6 ax - 3 dg, so the rest population drops out exactly:
 //   e - e_eq     = e(f) + 4 drho - 6 dpm - 3 rho u^2       (e_eq = -4 rho + 3 rho u^2 + 6 p_m)
 //   eps - eps_eq = eps(f) - 4 drho + 9 dpm + 3 rho u^2     (eps_eq = 4 rho - 3 rho u^2 - 9 p_m)
 //   q_i - q_i,eq = q_i(f) - (3 php - rho) u_i              (q_eq = (3 p_m - 2 rho) u, Eq. 27)
@@ -151,12 +160,12 @@ __device__ __forceinline__ void collide(T f[9], T rho, T drho, T ux, T uy, T Fx,
 // With D_k = -s_k (m_k - m_k,eq) + (1 - s_k/2)(S_k + C_k) (D_rho = 0, D_j = F for any
 // tau_c), f* = f + M^-1 D, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
 template <typename T>
-__device__ __forceinline__ void collide_mrt(T f[9], T rho, T drho, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
+__device__ __forceinline__ void collide_mrt(T f[9], T rho, T ux, T uy, T Fx, T Fy, T dpm, T php, T Cxx,
                                             T Cyy, T s_e, T s_eps, T s_q, T s_v) {
     const T ax = (f[1] + f[2]) + (f[3] + f[4]);
     const T dg = (f[5] + f[6]) + (f[7] + f[8]);
-    const T m_e = T(2) * dg - ax - T(4) * f[0];
-    const T m_eps = T(4) * f[0] - T(2) * ax + dg;
+    const T m_e4 = T(3) * ax + T(6) * dg;           // e(f) + 4 drho
+    const T m_eps4 = -(T(6) * ax + T(3) * dg);      // eps(f) - 4 drho
     const T m_qx = T(2) * (f[3] - f[1]) + ((f[5] - f[6]) + (f[8] - f[7]));
     const T m_qy = T(2) * (f[4] - f[2]) + ((f[5] + f[6]) - (f[7] + f[8]));
     const T m_pxx = (f[1] + f[3]) - (f[2] + f[4]);
@@ -164,9 +173,8 @@ __device__ __forceinline__ void collide_mrt(T f[9], T rho, T drho, T ux, T uy, T
     const T ru2 = rho * (ux * ux + uy * uy);
     const T uF = ux * Fx + uy * Fy;
     const T g = T(3) * php - rho;
-    const T d_e = -s_e * (m_e + T(4) * drho - T(6) * dpm - T(3) * ru2) +
-                  (T(1) - T(0.5) * s_e) * (T(6) * uF + T(3) * (Cxx + Cyy));
-    const T d_eps = -s_eps * (m_eps - T(4) * drho + T(9) * dpm + T(3) * ru2) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+    const T d_e = -s_e * (m_e4 - T(6) * dpm - T(3) * ru2) + (T(1) - T(0.5) * s_e) * (T(6) * uF + T(3) * (Cxx + Cyy));
+    const T d_eps = -s_eps * (m_eps4 + T(9) * dpm + T(3) * ru2) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
     const T hq = T(1) - T(0.5) * s_q;
     const T d_qx = -s_q * (m_qx - g * ux) - hq * Fx;
     const T d_qy = -s_q * (m_qy - g * uy) - hq * Fy;
@@ -274,7 +282,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     for (int a = 0; a < 9; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
+    // LDS holds the density as x = rho - rho_ref and the chemical potential minus
+    // muref.mu_off (float32: deviations from the reference state; float64: rho_ref
+    // = 0, offset 0)
+    constexpr bool F32 = sizeof(S) == 4;
     const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
+    const T phi0 = rho_ref * T(1.0 / 3.0) - pm_ref;      // float32: phi = phi0 + (x - (mu - mu_ref)) / 3
+    const MuRef muref(R, F32);
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
 
@@ -345,7 +359,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
         const int ly = ly0 + p * BY;
-        s_rho[(ly + 3) * W3 + lx0 + 3] = rho_ref + sum9(fown[p]);
+        s_rho[(ly + 3) * W3 + lx0 + 3] = sum9(fown[p]);
         s_a[(ly + 1) * W1 + lx0 + 1] = jx9(fown[p]);
         s_b[(ly + 1) * W1 + lx0 + 1] = own_mirror[p] ? -jy9(fown[p]) : jy9(fown[p]);
     }
@@ -354,7 +368,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         if (tid + q * NT < HALO) {
             const int pos = hpos[q];
             const int ly = pos / W3, lx = pos - ly * W3;
-            s_rho[pos] = rho_ref + sum9(fh[q]);
+            s_rho[pos] = sum9(fh[q]);
             if (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) {
                 s_a[(ly - 2) * W1 + lx - 2] = jx9(fh[q]);
                 s_b[(ly - 2) * W1 + lx - 2] = h_mirror[q] ? -jy9(fh[q]) : jy9(fh[q]);
@@ -368,10 +382,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     for (int k = tid; k < H2 * W2; k += NT) {
         const int lx = k % W2, ly = k / W2;
         const int c = (ly + 1) * W3 + lx + 1;
-        const T r = s_rho[c];
+        const T x = s_rho[c];
         const T L = lap<W3>(s_rho, c);
-        s_mu[k] = eos.mu(r) - kappa * L;
+        s_mu[k] = muref.dmu(eos, x) - kappa * L;
         if constexpr (PT) {
+            const T r = rho_ref + x;
             const T gx = ddx<W3>(s_rho, c), gy = ddy<W3>(s_rho, c);
             const T p = eos.p(r) - kappa * r * L - T(0.5) * kappa * (gx * gx + gy * gy);   // Eq. 4
             s_P[k] = p + kappa * gx * gx;                                                 // Eq. 5
@@ -386,7 +401,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int lx = k % W1, ly = k / W1;
         const int c2 = (ly + 1) * W2 + lx + 1;
         const int c3 = (ly + 2) * W3 + lx + 2;
-        const T r = s_rho[c3];
+        const T x = s_rho[c3];
+        const T r = rho_ref + x;
         T Fx, Fy;
         if constexpr (IMP) {
             const T g = T(1.0 / 3.0) - r;                                                 // Eq. 24
@@ -406,7 +422,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const T ux = (s_a[k] + T(0.5) * Fx) * ir;
         const T uy = (s_b[k] + T(0.5) * Fy) * ir;
         if constexpr (IMP) {
-            const T phi = r * T(1.0 / 3.0) - (c0 + s_mu[c2]) * T(1.0 / 3.0);             // Eq. 29
+            // Eq. 29: phi = rho/3 - p_m
+            const T phi = F32 ? phi0 + (x - s_mu[c2]) * T(1.0 / 3.0)
+                              : r * T(1.0 / 3.0) - (c0 + s_mu[c2]) * T(1.0 / 3.0);
             s_a[k] = phi * ux;
             s_b[k] = phi * uy;
         }
@@ -427,17 +445,19 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const int gx = x0 + lx0, gy = y0 + ly;
     if (gx < nx && gy < ny) {
         const int c3 = (ly + 3) * W3 + lx0 + 3, c2 = (ly + 2) * W2 + lx0 + 2, c1 = (ly + 1) * W1 + lx0 + 1;
-        const T r = s_rho[c3];
-        const T mu = s_mu[c2];
+        const T x = s_rho[c3];
+        const T r = rho_ref + x;
+        const T dmu = s_mu[c2];                                 // mu - mu_off
+        const double mu = muref.mu_off + (double)dmu;
         const T Fx = s_F[io], Fy = s_F[NN + io], ux = s_u[io], uy = s_u[NN + io];
-        const T drho = sum9(fo);
-        constexpr bool F32 = sizeof(S) == 4;
+        const T Sm = moving9(fo);
+        const T drho = fo[0] + Sm;
         const double m_in = F32 ? mass_in<9, T>(fo) : 0.0;      // exact node mass (float32 storage)
         const int node = gy * nx + gx;
         if constexpr (MODE == kFields) {
             const long long o = R.field_offset + node;
-            if (args.rho_out) args.rho_out[o] = (double)r;
-            if (args.mu_out) args.mu_out[o] = (double)mu;
+            if (args.rho_out) args.rho_out[o] = muref.rho_ref + (double)x;
+            if (args.mu_out) args.mu_out[o] = mu;
             if (args.u_out) {
                 args.u_out[o] = (double)ux;
                 args.u_out[args.field_total + o] = (double)uy;
@@ -445,9 +465,13 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         } else {
             T dpm, php, Cxx = T(0), Cyy = T(0);
             if constexpr (IMP) {
-                const T pm = (c0 + mu) * T(1.0 / 3.0);
-                dpm = (mu - mu_ref) * T(1.0 / 3.0);
-                php = pm - r * T(1.0 / 3.0);
+                if constexpr (F32) {
+                    dpm = dmu * T(1.0 / 3.0);
+                    php = -(phi0 + (x - dmu) * T(1.0 / 3.0));
+                } else {
+                    dpm = (dmu - mu_ref) * T(1.0 / 3.0);
+                    php = (c0 + dmu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+                }
                 Cxx = T(3) * ddx<W1>(s_a, c1);
                 Cyy = T(3) * ddy<W1>(s_b, c1);
             } else {
@@ -462,9 +486,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     const T nu = (T)R.nu;
                     s_v = IMP ? dev_rcp(nu * r * dev_rcp(pm_ref + dpm) + T(0.5)) : dev_rcp(T(3) * nu + T(0.5));
                 }
-                collide_mrt<T>(fo, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
+                collide_mrt<T>(fo, r, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
             } else {
-                collide<T>(fo, r, drho, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
+                collide<T>(fo, r, Sm, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
             }
             if constexpr (F32) keep_mass_on_axes<9, 4, T>(fo, m_in);
             if (plates && (gy == 0 || gy == ny - 1)) {
@@ -496,8 +520,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         acc.mx += (double)(r * ux);
         acc.my += (double)(r * uy);
         acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
-        acc.mumin = fmin(acc.mumin, (double)mu);
-        acc.mumax = fmax(acc.mumax, (double)mu);
+        acc.mumin = fmin(acc.mumin, mu);
+        acc.mumax = fmax(acc.mumax, mu);
         acc.status |= blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
     }
     }

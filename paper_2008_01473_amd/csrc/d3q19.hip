@@ -30,24 +30,30 @@ __device__ constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1,
 __device__ constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __device__ constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
-// Pull the 19 populations arriving at a node; X[k], Y[k], Z[k] (k = 0,1,2 for
-// offsets -1, 0, +1) are the wrapped x index, y*nx and z*nx*ny of the node's
-// neighbourhood.  Source of population a is x - e_a.
+// Pull the 19 populations arriving at a node (Eq. 10: population a comes from
+// x - e_a).  xy[k] is the byte offset of the in-plane neighbour (dx, dy) =
+// (k % 3 - 1, k / 3 - 1) within a plane, fixed over a sweep; zb[k] the byte offset
+// of plane z - 1 + k (wave-uniform), so each load costs one vector add.
 template <typename S, typename T>
-__device__ __forceinline__ void pull(const S* const (&p)[19], const int X[3], const int Y[3], const int Z[3],
-                                     T f[19]) {
+__device__ __forceinline__ void pull(const S* const (&p)[19], const int (&xy)[9], const int (&zb)[3], T f[19]) {
 #pragma unroll
     for (int a = 0; a < 19; ++a)
-        f[a] = (T)ld_off(p[a], (unsigned)(Z[1 - EZ[a]] + Y[1 - EY[a]] + X[1 - EX[a]]));
+        f[a] = (T)*reinterpret_cast<const S*>(reinterpret_cast<const char*>(p[a]) +
+                                             (unsigned)(xy[(1 - EY[a]) * 3 + (1 - EX[a])] + zb[1 - EZ[a]]));
 }
 
+// Sum of the moving populations, then the density deviation with the rest
+// population (the large deviation in float32 storage) added last: one rounding
+// at its magnitude.
 template <typename T>
-__device__ __forceinline__ T sum19(const T f[19]) {
-    T s0 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
-    T s1 = (f[7] + f[8]) + (f[9] + f[10]) + (f[11] + f[12]);
-    T s2 = (f[13] + f[14]) + (f[15] + f[16]) + (f[17] + f[18]);
+__device__ __forceinline__ T moving19(const T f[19]) {
+    const T s0 = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
+    const T s1 = (f[7] + f[8]) + (f[9] + f[10]) + (f[11] + f[12]);
+    const T s2 = (f[13] + f[14]) + (f[15] + f[16]) + (f[17] + f[18]);
     return s0 + (s1 + s2);
 }
+template <typename T>
+__device__ __forceinline__ T sum19(const T f[19]) { return f[0] + moving19(f); }
 template <typename T>
 __device__ __forceinline__ void mom19(const T f[19], T& jx, T& jy, T& jz) {
     jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
@@ -105,7 +111,8 @@ __device__ __forceinline__ T agz(F v) {
 }
 
 // BGK collision with Guo forcing and the correction term (improved scheme);
-// f holds populations minus fbar on entry and f* minus fbar on exit.
+// f holds populations minus fbar on entry and f* minus fbar on exit; Sm is the
+// moving populations' sum.
 // Equilibrium minus reference:
 //   rest: drho - 2 dpm - rho u^2 / 2
 //   axis: dpm / 6  + rho/18 (3 eu + 4.5 eu^2 - 1.5 u^2) - php eu
@@ -113,7 +120,7 @@ __device__ __forceinline__ T agz(F v) {
 // Correction (C_ii = 3 d_i, S = C_xx + C_yy + C_zz):
 //   rest -5S/21; +-i (C_ii - 6 (S - C_ii))/42; ij-edges (5 C_ii + 5 C_jj - 2 C_kk)/42.
 template <typename T>
-__device__ __forceinline__ void collide(T f[19], T rho, T drho, T ux, T uy, T uz, T Fx, T Fy, T Fz, T dpm,
+__device__ __forceinline__ void collide(T f[19], T rho, T Sm, T ux, T uy, T uz, T Fx, T Fy, T Fz, T dpm,
                                         T php, T Cxx, T Cyy, T Czz, T omega) {
     const T usq = ux * ux + uy * uy + uz * uz;
     const T uF = ux * Fx + uy * Fy + uz * Fz;
@@ -126,9 +133,10 @@ __device__ __forceinline__ void collide(T f[19], T rho, T drho, T ux, T uy, T uz
     const T Cxz = (T(7) * (Cxx + Czz) - T(2) * S) * k42;
     const T Cyz = (T(7) * (Cyy + Czz) - T(2) * S) * k42;
     {
-        const T feq = drho - T(2) * dpm - T(0.5) * rho * usq;
+        // f0* = f0 + omega (feq0 - f0) + om2 (G0 + C0), feq0 - f0 = Sm - 2 dpm - rho u^2 / 2
+        const T dfeq = Sm - T(2) * dpm - T(0.5) * rho * usq;
         const T G = T(1.0 / 3.0) * (T(-3) * uF);
-        f[0] = om1 * f[0] + omega * feq + om2 * (G + T(-5.0 / 21.0) * S);
+        f[0] += (omega * dfeq + om2 * (G + T(-5.0 / 21.0) * S));
     }
     // axis pairs: w = 1/18, php coefficient -1;  edge pairs: w = 1/36, +1/4
     const T Ua = dpm * T(1.0 / 6.0) - T(1.5) * r18 * usq;
@@ -174,7 +182,9 @@ __device__ __forceinline__ void equilibrium(T feq[19], T rho, T drho, T ux, T uy
 //      three iterations earlier, wait in a register FIFO when FIFO is set)
 // rho is kept for 4 slices (slot (z - z0 + 8) & 3); mu, j, psi and P for 3
 // (slot (z - z0 + 9) % 3); F and u of the tile for 2.
-template <typename S, typename T, int V, int BX, int BY, int MODE>
+// WT: store the populations at device scope (LBM_STORES_DEVICE) instead of
+// non-temporally; a template parameter so that each kernel holds one store loop.
+template <typename S, typename T, int V, int BX, int BY, int MODE, bool WT>
 __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     constexpr int NT = BX * BY;
     constexpr int W3 = BX + 6, H3 = BY + 6, A3 = W3 * H3;
@@ -213,20 +223,36 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     for (int a = 0; a < 19; ++a) pp[a] = src + (size_t)a * N;
     const Eos<T> eos{R.eos, (T)R.a, (T)R.b, (T)R.RT};
     const T kappa = (T)R.kappa, omega = (T)R.omega;
-    const T rho_ref = (T)R.rho_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
+    // LDS holds the density as x = rho - rho_ref and the chemical potential minus
+    // muref.mu_off (float32: deviations from the reference state; float64: rho_ref
+    // = 0, offset 0)
+    constexpr bool F32 = sizeof(S) == 4;
+    const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
+    const T phi0 = rho_ref * T(1.0 / 3.0) - pm_ref;      // float32: phi = phi0 + (x - (mu - mu_ref)) / 3
+    const MuRef muref(R, F32);
     const int x0 = tile.x0, y0 = tile.y0, z0 = tile.z0, zn = tile.zn;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
     const int gx0 = x0 + lx0, gy0 = y0 + ly0;
     const bool own_valid = gx0 < nx && gy0 < ny;
 
-    // wrapped x and y of the owned column and its neighbours (fixed over the sweep)
-    int OX[3], OY[3];
+    // byte offsets of the owned column's in-plane neighbourhood (fixed over the sweep)
+    constexpr int WS = (int)sizeof(S);
+    int oxy[9];
+    {
+        int X[3], Y[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        OX[k] = wrap(gx0 - 1 + k, nx, sx);
-        OY[k] = wrap(gy0 - 1 + k, ny, sy) * nx;
+        for (int k = 0; k < 3; ++k) {
+            X[k] = wrap(gx0 - 1 + k, nx, sx);
+            Y[k] = wrap(gy0 - 1 + k, ny, sy) * nx;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) oxy[k] = (Y[k / 3] + X[k % 3]) * WS;
     }
+    auto zbytes = [&](int z, int (&zb)[3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) zb[k] = wrap(z - 1 + k, nz, sz) * NXY * WS;
+    };
 
     T fifo[FIFO ? 4 : 1][19];
     DiagAcc acc;
@@ -236,7 +262,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     // decoded once here (idle lanes repeat the last halo node and store nothing).
     constexpr int HALO = A3 - NT;
     constexpr int HP = (HALO + NT - 1) / NT;
-    int hX[HP][3], hY[HP][3], hpos[HP], hpos1[HP];
+    int hxy[HP][9], hpos[HP], hpos1[HP];
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
         int k = tid + q * NT;
@@ -254,11 +280,14 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             lx = c < 3 ? c : W3 - 6 + c;
         }
         const int hx = x0 - 3 + lx, hy = y0 - 3 + ly;
+        int X[3], Y[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            hX[q][d] = wrap(hx - 1 + d, nx, sx);
-            hY[q][d] = wrap(hy - 1 + d, ny, sy) * nx;
+            X[d] = wrap(hx - 1 + d, nx, sx);
+            Y[d] = wrap(hy - 1 + d, ny, sy) * nx;
         }
+#pragma unroll
+        for (int d = 0; d < 9; ++d) hxy[q][d] = (Y[d / 3] + X[d % 3]) * WS;
         hpos[q] = (tid + q * NT < HALO) ? ly * W3 + lx : -1;
         hpos1[q] = (lx >= 2 && lx < W3 - 2 && ly >= 2 && ly < H3 - 2) ? (ly - 2) * W1 + lx - 2 : -1;
     }
@@ -271,9 +300,6 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         constexpr int KW = decltype(slot)::value;
         constexpr int KR = (KW + 1) & 3;
         const int za = z0 - 3 + it;
-        int Z[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Z[k] = wrap(za - 1 + k, nz, sz) * NXY;
         const int slA = (za - z0 + 8) & 3;
         const int slA3 = (za - z0 + 9) % 3;
 
@@ -282,12 +308,14 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         if (it < NIT) {
             T f[19];
             T fh[HP][19];
-            pull<S, T>(pp, OX, OY, Z, f);
+            int zb[3];
+            zbytes(za, zb);
+            pull<S, T>(pp, oxy, zb, f);
 #pragma unroll
             for (int q = 0; q < HP; ++q)
                 if ((tid & ~63) + q * NT < HALO)          // waves with no halo node left skip the pulls
-                    pull<S, T>(pp, hX[q], hY[q], Z, fh[q]);
-            s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = rho_ref + sum19(f);
+                    pull<S, T>(pp, hxy[q], zb, fh[q]);
+            s_rho[slA * A3 + (ly0 + 3) * W3 + lx0 + 3] = sum19(f);
             T jx, jy, jz;
             mom19(f, jx, jy, jz);
             const int c1 = slA3 * A1 + (ly0 + 1) * W1 + lx0 + 1;
@@ -299,7 +327,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
             for (int q = 0; q < HP; ++q) {
                 if (hpos[q] >= 0) {
-                    s_rho[slA * A3 + hpos[q]] = rho_ref + sum19(fh[q]);
+                    s_rho[slA * A3 + hpos[q]] = sum19(fh[q]);
                     if (hpos1[q] >= 0) {
                         T hx_, hy_, hz_;
                         mom19(fh[q], hx_, hy_, hz_);
@@ -321,10 +349,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             for (int k = tid; k < A2; k += NT) {
                 const int lx = k % W2, ly = k / W2;
                 const int c = (ly + 1) * W3 + lx + 1;
-                const T r = Rp[c];
+                const T x = Rp[c];
                 const T L = lap<W3>(Rd, Rp, Ru, c);
-                s_mu[slB * A2 + k] = eos.mu(r) - kappa * L;
+                s_mu[slB * A2 + k] = muref.dmu(eos, x) - kappa * L;
                 if constexpr (PT) {
+                    const T r = rho_ref + x;
                     const T g0 = gx<W3>(Rd, Rp, Ru, c), g1 = gy<W3>(Rd, Rp, Ru, c), g2 = gz<W3>(Rd, Rp, Ru, c);
                     // Eq. 4; the tensor of Eq. 5 is rebuilt from (p, grad rho) where it is differentiated
                     const T p = eos.p(r) - kappa * r * L - T(0.5) * kappa * (g0 * g0 + g1 * g1 + g2 * g2);
@@ -350,7 +379,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 if (IMP) { lx = k % W1; ly = k / W1; } else { lx = k % BX + 1; ly = k / BX + 1; }
                 const int c2 = (ly + 1) * W2 + lx + 1;
                 const int c3 = (ly + 2) * W3 + lx + 2;
-                const T r = s_rho[sp * A3 + c3];
+                const T x = s_rho[sp * A3 + c3];
+                const T r = rho_ref + x;
                 T Fx, Fy, Fz;
                 const T* Md = s_mu + md * A2;
                 const T* Mp = s_mu + mp * A2;
@@ -394,7 +424,9 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 const T uy = (s_j[3 * A1 + c1] + T(0.5) * Fy) * ir;
                 const T uz = (s_j[6 * A1 + c1] + T(0.5) * Fz) * ir;
                 if constexpr (IMP) {
-                    const T phi = r * T(1.0 / 3.0) - (c0 + Mp[c2]) * T(1.0 / 3.0);      // Eq. 29
+                    // Eq. 29: phi = rho/3 - p_m
+                    const T phi = F32 ? phi0 + (x - Mp[c2]) * T(1.0 / 3.0)
+                                      : r * T(1.0 / 3.0) - (c0 + Mp[c2]) * T(1.0 / 3.0);
                     s_psi[c1] = phi * ux;
                     s_psi[3 * A1 + c1] = phi * uy;
                     s_psi[6 * A1 + c1] = phi * uz;
@@ -414,8 +446,10 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             const int sp = (zd - z0 + 8) & 3;
             const int md = (zd - 1 - z0 + 9) % 3, mp = (zd - z0 + 9) % 3, mu3 = (zd + 1 - z0 + 9) % 3;
             const int sfu = (zd - z0 + 8) & 1;
-            const T r = s_rho[sp * A3 + (ly0 + 3) * W3 + lx0 + 3];
-            const T mu = s_mu[mp * A2 + (ly0 + 2) * W2 + lx0 + 2];
+            const T x = s_rho[sp * A3 + (ly0 + 3) * W3 + lx0 + 3];
+            const T r = rho_ref + x;
+            const T dmu = s_mu[mp * A2 + (ly0 + 2) * W2 + lx0 + 2];    // mu - mu_off
+            const double mu = muref.mu_off + (double)dmu;
             const T* fu = s_fu + sfu * 6 * NT + tid;
             const T Fx = fu[0], Fy = fu[NT], Fz = fu[2 * NT], ux = fu[3 * NT], uy = fu[4 * NT], uz = fu[5 * NT];
             T f[19];
@@ -423,19 +457,18 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
                 for (int a = 0; a < 19; ++a) f[a] = fifo[KR][a];
             } else {
-                int Zd[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) Zd[k] = wrap(zd - 1 + k, nz, sz) * NXY;
-                pull<S, T>(pp, OX, OY, Zd, f);
+                int zb[3];
+                zbytes(zd, zb);
+                pull<S, T>(pp, oxy, zb, f);
             }
-            const T drho = sum19(f);
-            constexpr bool F32 = sizeof(S) == 4;
+            const T Sm = moving19(f);
+            const T drho = f[0] + Sm;
             const double m_in = F32 ? mass_in<19, T>(f) : 0.0;    // exact node mass (float32 storage)
             const int node = zd * NXY + gy0 * nx + gx0;
             if constexpr (MODE == kFields) {
                 const long long o = R.field_offset + node;
-                if (args.rho_out) args.rho_out[o] = (double)r;
-                if (args.mu_out) args.mu_out[o] = (double)mu;
+                if (args.rho_out) args.rho_out[o] = muref.rho_ref + (double)x;
+                if (args.mu_out) args.mu_out[o] = mu;
                 if (args.u_out) {
                     args.u_out[o] = (double)ux;
                     args.u_out[args.field_total + o] = (double)uy;
@@ -451,15 +484,20 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                     Cxx = T(3) * gx<W1>(Xd, Xp, Xu, c1);
                     Cyy = T(3) * gy<W1>(Yd, Yp, Yu, c1);
                     Czz = T(3) * gz<W1>(Zdd, Zp, Zu, c1);
-                    dpm = (mu - mu_ref) * T(1.0 / 3.0);
-                    php = (c0 + mu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+                    if constexpr (F32) {
+                        dpm = dmu * T(1.0 / 3.0);
+                        php = -(phi0 + (x - dmu) * T(1.0 / 3.0));
+                    } else {
+                        dpm = (dmu - mu_ref) * T(1.0 / 3.0);
+                        php = (c0 + dmu) * T(1.0 / 3.0) - r * T(1.0 / 3.0);
+                    }
                 } else {
                     dpm = drho * T(1.0 / 3.0);
                     php = T(0);
                 }
-                collide<T>(f, r, drho, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
+                collide<T>(f, r, Sm, ux, uy, uz, Fx, Fy, Fz, dpm, php, Cxx, Cyy, Czz, omega);
                 if constexpr (F32) keep_mass_on_axes<19, 6, T>(f, m_in);
-                if (args.write_through) {
+                if constexpr (WT) {
 #pragma unroll
                     for (int a = 0; a < 19; ++a) st_dev(dst + (size_t)a * N, (unsigned)node, (S)f[a]);
                 } else {
@@ -472,8 +510,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             acc.my += (double)(r * uy);
             acc.mz += (double)(r * uz);
             acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy + uz * uz));
-            acc.mumin = fmin(acc.mumin, (double)mu);
-            acc.mumax = fmax(acc.mumax, (double)mu);
+            acc.mumin = fmin(acc.mumin, mu);
+            acc.mumax = fmax(acc.mumax, mu);
             acc.status |= blowup_bits<T>(r, ux, uy, uz, R.rho_max);
         }
         __syncthreads();
@@ -577,12 +615,17 @@ hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
     if constexpr (sizeof(T) == 8 && BX * BY > 256) {
         return hipErrorInvalidValue;      // float64 rings of this tile exceed the 160 KB of LDS
     } else {
+    const dim3 g(grid), b(BX * BY);
     if (mode == kFields)
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kFields>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kFields, false>), g, b, 0, s, a);
+    else if (mode == kStepDiag && a.write_through)
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag, true>), g, b, 0, s, a);
     else if (mode == kStepDiag)
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag, false>), g, b, 0, s, a);
+    else if (a.write_through)
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep, true>), g, b, 0, s, a);
     else
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep>), dim3(grid), dim3(BX * BY), 0, s, a);
+        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep, false>), g, b, 0, s, a);
     return hipGetLastError();
     }
 }

@@ -86,6 +86,37 @@ __device__ __forceinline__ void st_dev(S* base, unsigned idx, S v) {
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Buffer access to one population array.  A descriptor covers the array (base,
+// size in bytes); an access adds a per-lane byte offset (vector register) and a
+// wave-uniform byte offset (scalar register), so that a pull whose lane offsets
+// are fixed over a sweep costs no vector arithmetic.  The hardware returns 0 for
+// loads and drops stores beyond the array.
+constexpr int kRawBufferDword3 = 0x00020000;   // untyped 32-bit data, gfx9-family descriptor word 3
+constexpr int kBufNonTemporal = 2;             // cache policy bits: nt
+constexpr int kBufDeviceScope = 16;            // sc1: written through to the device coherence point
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferDword3);
+}
+template <typename S>
+__device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <int AUX>
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, AUX);
+}
+
 // Periodic wrap of a coordinate that is at most a few nodes outside [0, n).
 // `slow` is set by the host when n is too small for one conditional correction.
 __device__ __forceinline__ int wrap(int v, int n, int slow) {
@@ -127,6 +158,52 @@ __device__ __forceinline__ T Eos<T>::mu(T rho) const {
     const T iom3 = iom * iom * iom;
     return RT * (dev_logf(rho) + T(1) + h * (T(8) - T(9) * h + T(3) * h * h) * iom3) - T(2) * a * rho;
 }
+
+// Chemical potential in the step kernels' LDS.  Float32 kernels keep density and
+// chemical potential as deviations from the lattice's reference state, x = rho -
+// rho_ref and mu - mu_ref, and evaluate the bulk part mu_EOS(rho_ref + x) - mu_ref
+// in float64 from the exact density.  The float32 evaluation's error (about 1e-7:
+// rho rounded to float32 at ~8, cancellation between the EOS terms) drives spurious
+// velocities ten times above those that the float32 storage itself leaves (measured
+// on the 512^2 droplet: 2.9e-6 against 2.5e-7), while the deviation of the result
+// is small and rounds to float32 well below 1e-8.  Float64 kernels keep rho and mu
+// themselves (rho_ref = 0, no offset).
+#ifndef LBM_MU_FLOAT64
+#define LBM_MU_FLOAT64 0
+#endif
+struct MuRef {
+    int kind;
+    double a, b, RT, rho_ref, mu_off, q0, k0;
+    __device__ __forceinline__ MuRef(const LatticeRec& R, bool f32)
+        : kind(R.eos), a(R.a), b(R.b), RT(R.RT), rho_ref(R.rho_ref), mu_off(f32 ? R.mu_ref : 0.0), q0(R.dev_q0),
+          k0(R.dev_k0) {}
+    // bulk chemical potential minus the LDS offset at density rho_ref + x
+    template <typename T>
+    __device__ __forceinline__ T dmu(const Eos<T>& eos, T x) const {
+        if constexpr (sizeof(T) == 4) {
+            if constexpr (LBM_MU_FLOAT64) {
+                const Eos<double> e{kind, a, b, RT};
+                return (T)(e.mu(rho_ref + (double)x) - mu_off);
+            } else {
+                // float32 in deviation form: with q = 1/(1 - b rho) (vdW) the x-dependent
+                // parts are RT [ln(rho q) + b x q q0] - 2 a x; with q = 1/(1 - h), h = b rho/4
+                // (CS) they are RT [ln rho + g(h) - g(h0)] - 2 a x, g = 2 q^3 + q^2 - 3, and
+                // g(h) - g(h0) = (h - h0) q q0 (2 (q^2 + q q0 + q0^2) + q + q0); k0 holds the rest
+                const T rt = (T)RT, bb = (T)b, qq0 = (T)q0, r = (T)rho_ref + x;
+                if (kind == 0) {
+                    const T q = dev_rcp(dev_rcp(qq0) - bb * x);
+                    return (T)k0 + rt * (dev_logf(r * q) + bb * x * q * qq0) - T(2) * (T)a * x;
+                }
+                const T dh = T(0.25) * bb * x;
+                const T q = dev_rcp(dev_rcp(qq0) - dh);
+                const T g = dh * q * qq0 * (T(2) * (q * q + q * qq0 + qq0 * qq0) + q + qq0);
+                return (T)k0 + rt * (dev_logf(r) + g) - T(2) * (T)a * x;
+            }
+        } else {
+            return eos.mu(x);
+        }
+    }
+};
 
 // Block -> tile mapping that keeps spatially adjacent tiles on one XCD: work
 // groups are dealt to the 8 XCDs round-robin, so block b runs on XCD b % 8 and
@@ -214,7 +291,9 @@ __device__ __forceinline__ void pair_update(T& fp, T& fm, T eu, T eF, T e0, T e1
 // only).  Without it, per-step changes smaller than half an ulp of the large rest
 // deviation (~|rho - rho_ref|) are rounded away in the same direction at every node
 // of a slowly relaxing bulk and the lattice drifts in mass (measured: 1e-4 over 5e4
-// steps at 512^2).
+// steps at 512^2).  The collisions update the rest population in increment form,
+// f0 + d0 with d0 formed from small quantities only, so that its one large rounding
+// is that of the stored value.
 template <int Q, typename T>
 __device__ __forceinline__ double mass_in(const T (&f)[Q]) {
     double m = 0;

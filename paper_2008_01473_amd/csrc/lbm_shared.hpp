@@ -42,6 +42,10 @@ struct LatticeRec {
     int walls, pad_walls;
     double wall_u0, wall_u1;
     double c0;                          // improved scheme: p_m = (c0 + mu)/3 (the paper: 1)
+    // Float32 chemical potential in deviation form (see MuRef): q0 = 1/(1 - b rho_ref)
+    // (vdW) or 1/(1 - b rho_ref / 4) (CS), and the constant part k0 of
+    // mu_EOS(rho_ref + x) - mu_ref that does not depend on x.
+    double dev_q0, dev_k0;
 };
 
 // Chaining flags of consecutive adjoint steps (adjoint_launch).
