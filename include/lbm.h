@@ -266,6 +266,24 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
                      double* grad);
 int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar,
                        double* lam_out, void* ws, double* grad);
+/* lbm_adjoint_step_noalloc: lbm_adjoint_step for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and the same result, bit for bit, with
+ * the workspace taken from a fixed array in each GPU's global memory instead of
+ * the caller's `ws`.  The array holds lbm_adjoint_noalloc_max_bytes() bytes (24
+ * MiB: D2Q9 lattices up to about 120 000 nodes, e.g. 256 x 256 or 345 x 345) on
+ * every GPU the library runs on, until the process ends; a lattice whose
+ * workspace (lbm_adjoint_workspace_bytes) is larger gets LBM_ERR_UNSUPPORTED.
+ * The first call on a device resolves the array's address (hipGetSymbolAddress);
+ * no call allocates.  Every call on one GPU uses the same array, and each call
+ * overwrites what the previous one left there (nothing in it needs to start at
+ * zero): calls that overlap in time on one GPU (two streams, two host threads)
+ * race on it and must be serialised by the caller.  Arguments, errors and the
+ * increment of grad as for lbm_adjoint_step. */
+int lbm_adjoint_step_noalloc(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out,
+                             double* grad);
+size_t lbm_adjoint_noalloc_max_bytes(void);
+
 /* lbm_adjoint_segment: one checkpoint segment of a checkpointed backward pass.
  * Copies `checkpoint` (raw state of time level t0, lbm_get_state layout) into
  * the first of the m >= 1 slots of `states` (device, m * lbm_state_bytes,

@@ -66,6 +66,8 @@ SIGNATURES = {
     "lbm_adjoint_segment": (c_int, [c_void_p, c_void_p, c_longlong, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p]),
     "lbm_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lbm_adjoint_step_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lbm_adjoint_noalloc_max_bytes": (c_size_t, []),
     "lbm_adjoint_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_init": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_set_tile_shape": (c_int, [c_void_p, c_int]),

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "lbm_device.hpp"
 #include "lbm_shared.hpp"
@@ -545,6 +546,39 @@ size_t adjoint_workspace_doubles(int nx, int ny) {
     const long long tiles = (long long)((nx + adj::TX - 1) / adj::TX) * ((ny + adj::TY - 1) / adj::TY);
     const long long blocks = std::max<long long>((N + 255) / 256, tiles);
     return (size_t)adj::NFIELDS * (size_t)N + 2 * (size_t)blocks;
+}
+
+// Device workspace of the allocation-free adjoint step (lbm_adjoint_step_noalloc):
+// a fixed array in each GPU's global memory, held until the process ends.  In host
+// code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and is kept here.
+constexpr size_t kStaticScratchBytes = size_t(24) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+// Device address of the current device's scratch array (resolved on the first
+// call per device; later calls return the kept address).
+hipError_t static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 // kind: 0 step, 1 fields (rho_bar/u_bar given), 2 init.  chain (steps of a

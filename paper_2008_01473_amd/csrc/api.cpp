@@ -37,6 +37,8 @@ hipError_t launch_finalize(const DiagPartial* partial, const LatticeRec* recs, c
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t adjoint_workspace_doubles(int nx, int ny);
+size_t static_scratch_bytes();
+hipError_t static_scratch(void** out);
 hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int precision, int improved, const void* state,
                           const double* lam_in, double* lam_out, const double* rho_bar, const double* u_bar,
                           const double* rho0, double* grad_rho0, double* ws, double* grad, hipStream_t s,
@@ -951,6 +953,27 @@ int lbm_adjoint_step(lbm_ctx* h, const void* state_t, const double* lam_next, do
                            h->stream, 0));
     return LBM_OK;
 }
+
+int lbm_adjoint_step_noalloc(lbm_ctx* h, const void* state_t, const double* lam_next, double* lam_out,
+                             double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!state_t || !lam_next || !lam_out || !grad) return fail(LBM_ERR_ARG, "null argument");
+    if (lam_next == lam_out) return fail(LBM_ERR_ARG, "lam_next and lam_out must not alias");
+    const size_t need = adjoint_workspace_doubles(h->recs[0].nx, h->recs[0].ny) * sizeof(double);
+    if (need > static_scratch_bytes())
+        return fail(LBM_ERR_UNSUPPORTED, "this lattice's adjoint workspace (" + std::to_string(need) +
+                                             " bytes) exceeds the static scratch of " +
+                                             std::to_string(static_scratch_bytes()) + " bytes");
+    void* ws = nullptr;
+    HIP_TRY(static_scratch(&ws));
+    HIP_TRY(adjoint_launch(0, h->recs[0], adjoint_dRT(h), h->precision, h->variant == kImproved, state_t, lam_next,
+                           lam_out, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<double*>(ws), grad,
+                           h->stream, 0));
+    return LBM_OK;
+}
+
+size_t lbm_adjoint_noalloc_max_bytes(void) { return static_scratch_bytes(); }
 
 namespace {
 
