@@ -439,18 +439,29 @@ def cpu_baseline(torch, inputs, seconds):
     m = oeos.maxwell(E, 0.8)
     rho0 = inputs.droplet((512, 512), m["rho_g"], m["rho_l"], 80.0, 5.0, noise=0.0)
     prm = model.Params(lattice="D2Q9", eos=E, T_over_Tc=0.8, kappa=0.01, tau=0.8, scheme="improved")
-    f = model.init(torch.as_tensor(rho0), prm)
-    f = model.step(f, prm)      # first-call overheads outside the timing
-    n, t0 = 0, time.perf_counter()
-    while True:
-        f = model.step(f, prm)
-        n += 1
-        el = time.perf_counter() - t0
-        if (el >= seconds and n >= 2) or n >= 2000:
-            break
-    return {"value": 512 * 512 * n / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": f"{n} steps of the 512x512 D2Q9 CS droplet (improved, float64), "
-                                        f"{el:.1f} s on {torch.get_num_threads()} threads of {model_name}"}
+
+    def timed(secs):
+        f = model.init(torch.as_tensor(rho0), prm)
+        f = model.step(f, prm)      # first-call overheads outside the timing
+        n, t0 = 0, time.perf_counter()
+        while True:
+            f = model.step(f, prm)
+            n += 1
+            el = time.perf_counter() - t0
+            if (el >= secs and n >= 2) or n >= 2000:
+                return n, el
+
+    n, el = timed(seconds)
+    out = {"value": 512 * 512 * n / el / 1e6, "unit": "MLUPS", "cores": threads,
+           "kind": "oracle", "sample": f"{n} steps of the 512x512 D2Q9 CS droplet (improved, float64), "
+                                       f"{el:.1f} s on {threads} threads of {model_name}"}
+    # the same oracle on one thread
+    torch.set_num_threads(1)
+    n1, el1 = timed(seconds / 3)
+    torch.set_num_threads(threads)
+    out["single_thread"] = {"value": 512 * 512 * n1 / el1 / 1e6, "unit": "MLUPS", "cores": 1,
+                            "sample": f"{n1} steps, {el1:.1f} s on 1 thread"}
+    return out
 
 
 def main():
