@@ -297,6 +297,29 @@ size_t lbm_adjoint_noalloc_max_bytes(void);
  * left at time level t0 + m with no diagnostics.  Same support as the calls above. */
 int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m, void* states, double* lam,
                         double* lam2, void* ws, double* grad);
+
+/* lbm_adjoint_sweep: every segment of a checkpointed backward pass in one call,
+ * the recomputation of a segment overlapped with the adjoint steps of the one
+ * after it.  Segment i (0 <= i < nseg, nseg >= 1) starts from checkpoints[i], the
+ * raw state of time level t0[i] (device pointer, lbm_get_state layout, 16-byte
+ * aligned), and covers m[i] >= 1 steps; the segments must be consecutive
+ * (t0[i+1] = t0[i] + m[i]).  checkpoints, t0 and m are host arrays of nseg
+ * entries.  `states` (device, caller-owned, overwritten, 16-byte aligned) holds
+ * two arenas of kmax = max m[i] slots: 2 * kmax * lbm_state_bytes.  From the last
+ * segment to the first, each segment's states t0[i] .. t0[i]+m[i]-1 are recomputed
+ * into arena i % 2 on a second stream of the library's own (default priority)
+ * while the adjoint steps of segment i+1 run on the handle's stream over the
+ * other arena; events order the two streams, and the second stream starts after
+ * the work already queued on the handle's stream.  lam, lam2, ws and grad as in
+ * lbm_adjoint_segment: on entry lam holds dL/df(t0[nseg-1] + m[nseg-1]), on exit
+ * dL/df(t0[0]); the results equal those of lbm_adjoint_segment called for
+ * i = nseg-1 .. 0 bit for bit.  When the call returns, all its work is queued on
+ * the handle's stream (synchronising that stream covers the second one).  The
+ * handle's own state and time level are not changed; blow-up flags are cleared.
+ * Graphs (lbm_set_use_graphs) are captured per (kind, segment length, arena,
+ * buffers) and replayed.  Same support as the calls above. */
+int lbm_adjoint_sweep(lbm_ctx* h, const void* const* checkpoints, const long long* t0, const int* m, int nseg,
+                      void* states, double* lam, double* lam2, void* ws, double* grad);
 int lbm_adjoint_init(lbm_ctx* h, const double* rho0, const double* lam0, double* grad_rho0, void* ws,
                      double* grad);
 

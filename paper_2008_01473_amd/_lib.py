@@ -65,6 +65,8 @@ SIGNATURES = {
     "lbm_adjoint_workspace_bytes": (c_size_t, [c_void_p]),
     "lbm_adjoint_segment": (c_int, [c_void_p, c_void_p, c_longlong, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p]),
+    "lbm_adjoint_sweep": (c_int, [c_void_p, P(c_void_p), P(c_longlong), P(c_int), c_int, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_step_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_noalloc_max_bytes": (c_size_t, []),

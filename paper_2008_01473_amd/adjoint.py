@@ -8,13 +8,14 @@ adjoint kernels and sqrt(N) checkpointing of the forward states.
     loss.backward()                         # rho0.grad, kappa.grad, T_over_Tc.grad
 
 Forward: lbm_init, then n steps; the raw state is checkpointed every k = ceil(sqrt(n))
-steps.  Backward: dL/df(N) from lbm_adjoint_fields, then segment by segment in
-reverse lbm_adjoint_segment (restore the checkpoint, recompute and keep the
-segment's states, run the adjoint steps back through them); finally
-lbm_adjoint_init gives dL/drho0.  All of this runs in the HIP kernels and the
-library's runtime; this module orders the calls.
+steps.  Backward: dL/df(N) from lbm_adjoint_fields, then lbm_adjoint_sweep runs the
+segments in reverse (restore a checkpoint, recompute the segment's states on a
+second stream while the adjoint steps of the later segment run, then the adjoint
+steps back through them); finally lbm_adjoint_init gives dL/drho0.  All of this
+runs in the HIP kernels and the library's runtime; this module orders the calls.
 """
 
+import ctypes
 import math
 
 import torch
@@ -73,11 +74,16 @@ class Rollout:
         check(L.lbm_adjoint_fields(sim.h, self.final_state.data_ptr(), None if rb is None else rb.data_ptr(),
                                    None if ub is None else ub.data_ptr(), lam.data_ptr(), ws, grad.data_ptr()),
               "lbm_adjoint_fields")
-        states = torch.empty(self.k * sim.state_bytes, dtype=torch.uint8, device=dev)
-        for t0 in sorted(self.checkpoints, reverse=True):
-            m = min(self.k, self.n - t0)
-            check(L.lbm_adjoint_segment(sim.h, self.checkpoints[t0].data_ptr(), t0, m, states.data_ptr(),
-                                        lam.data_ptr(), lam2.data_ptr(), ws, grad.data_ptr()), "lbm_adjoint_segment")
+        t0s = sorted(self.checkpoints)
+        nseg = len(t0s)
+        ms = [min(self.k, self.n - t) for t in t0s]
+        if nseg:
+            # two arenas: one segment's recomputation overlaps the next one's adjoint steps
+            states = torch.empty(2 * max(ms) * sim.state_bytes, dtype=torch.uint8, device=dev)
+            ck = (ctypes.c_void_p * nseg)(*[self.checkpoints[t].data_ptr() for t in t0s])
+            check(L.lbm_adjoint_sweep(sim.h, ck, (ctypes.c_longlong * nseg)(*t0s), (ctypes.c_int * nseg)(*ms), nseg,
+                                      states.data_ptr(), lam.data_ptr(), lam2.data_ptr(), ws, grad.data_ptr()),
+                  "lbm_adjoint_sweep")
         grad_rho0 = torch.empty(self.N, dtype=torch.float64, device=dev)
         check(L.lbm_adjoint_init(sim.h, self.rho0.data_ptr(), lam.data_ptr(), grad_rho0.data_ptr(), ws,
                                  grad.data_ptr()), "lbm_adjoint_init")

@@ -89,17 +89,17 @@ __device__ __forceinline__ int at(const Nbr& n, int dx, int dy, int nx) {
 // Eq. 17 gradient components and the isotropic Laplacian of a global field.
 __device__ __forceinline__ double ddx(const double* p, const Nbr& n, int nx) {
     return (4.0 * (p[at(n, 1, 0, nx)] - p[at(n, -1, 0, nx)]) + (p[at(n, 1, 1, nx)] - p[at(n, -1, 1, nx)]) +
-            (p[at(n, 1, -1, nx)] - p[at(n, -1, -1, nx)])) / 12.0;
+            (p[at(n, 1, -1, nx)] - p[at(n, -1, -1, nx)])) * (1.0 / 12.0);
 }
 __device__ __forceinline__ double ddy(const double* p, const Nbr& n, int nx) {
     return (4.0 * (p[at(n, 0, 1, nx)] - p[at(n, 0, -1, nx)]) + (p[at(n, 1, 1, nx)] + p[at(n, -1, 1, nx)]) -
-            (p[at(n, -1, -1, nx)] + p[at(n, 1, -1, nx)])) / 12.0;
+            (p[at(n, -1, -1, nx)] + p[at(n, 1, -1, nx)])) * (1.0 / 12.0);
 }
 __device__ __forceinline__ double lap(const double* p, const Nbr& n, int nx) {
     const int c = n.y * nx + n.x;
     return (4.0 * (p[at(n, 1, 0, nx)] + p[at(n, -1, 0, nx)] + p[at(n, 0, 1, nx)] + p[at(n, 0, -1, nx)]) +
-            (p[at(n, 1, 1, nx)] + p[at(n, -1, 1, nx)] + p[at(n, -1, -1, nx)] + p[at(n, 1, -1, nx)]) - 20.0 * p[c]) /
-           6.0;
+            (p[at(n, 1, 1, nx)] + p[at(n, -1, 1, nx)] + p[at(n, -1, -1, nx)] + p[at(n, 1, -1, nx)]) - 20.0 * p[c]) *
+           (1.0 / 6.0);
 }
 
 // mu_EOS, d mu_EOS / d rho and d mu_EOS / d(T/Tc) for the two free energies.
@@ -107,18 +107,22 @@ __device__ __forceinline__ double lap(const double* p, const Nbr& n, int nx) {
 __device__ __forceinline__ void eos_terms(const LatticeRec& R, double dRT, double rho, double& mu,
                                           double& dmu_drho, double& dmu_dt) {
     const double RT = R.RT, a = R.a, b = R.b;
+    // one reciprocal of (1 - b rho) or (1 - h) and one of rho; the kernels' float64
+    // logarithm (log_pos)
+    const double ir = 1.0 / rho;
     if (R.eos == 0) {
-        const double br = 1.0 - b * rho;
-        const double s = log(rho / br) + 1.0 / br;
+        const double ibr = 1.0 / (1.0 - b * rho);
+        const double s = log_pos(rho * ibr) + ibr;
         mu = RT * s - 2.0 * a * rho;
-        dmu_drho = RT / (rho * br * br) - 2.0 * a;
+        dmu_drho = RT * ir * (ibr * ibr) - 2.0 * a;
         dmu_dt = dRT * s;
     } else {
-        const double h = 0.25 * b * rho, om = 1.0 - h;
-        const double s = log(rho) + 1.0 + h * (8.0 - 9.0 * h + 3.0 * h * h) / (om * om * om);
+        const double h = 0.25 * b * rho, iom = 1.0 / (1.0 - h);
+        const double iom3 = iom * iom * iom;
+        const double s = log_pos(rho) + 1.0 + h * (8.0 - 9.0 * h + 3.0 * h * h) * iom3;
         mu = RT * s - 2.0 * a * rho;
         const double num = 1.0 + 4.0 * h + 4.0 * h * h - 4.0 * h * h * h + h * h * h * h;
-        dmu_drho = RT * num / (rho * om * om * om * om) - 2.0 * a;
+        dmu_drho = RT * num * ir * (iom3 * iom) - 2.0 * a;
         dmu_dt = dRT * s;
     }
 }
@@ -155,8 +159,8 @@ __global__ void fwd_mu(AdjArgs a, int from_rho0) {
 __device__ __forceinline__ void collision_vjp(const AdjArgs& a, int i, const double (&lam)[9], double r, double ux,
                                               double uy, double Fx, double Fy, double mu) {
     const double w = a.rec.omega, w2 = 1.0 - 0.5 * w;
-    const double pm = a.improved ? (a.rec.c0 + mu) / 3.0 : r / 3.0;
-    const double php = pm - r / 3.0;
+    const double pm = a.improved ? (a.rec.c0 + mu) * (1.0 / 3.0) : r * (1.0 / 3.0);
+    const double php = pm - r * (1.0 / 3.0);
     const double usq = ux * ux + uy * uy;
     double rb = 0, uxb = 0, uyb = 0, pb = 0, fxb = 0, fyb = 0, cxxb = 0, cyyb = 0;
     for (int q = 0; q < 9; ++q) {
@@ -173,7 +177,7 @@ __device__ __forceinline__ void collision_vjp(const AdjArgs& a, int i, const dou
         } else {
             const double wq = W[q];
             const double k = (q < 5) ? -0.5 : 0.25;             // coefficient of php * eu
-            rb += fe * (wq * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq) - k * eu / 3.0);
+            rb += fe * (wq * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq) - k * eu * (1.0 / 3.0));
             pb += fe * ((q < 5 ? 1.0 / 3.0 : 1.0 / 12.0) + k * eu);
             uxb += fe * (r * wq * (3.0 * ex + 9.0 * eu * ex - 3.0 * ux) + k * php * ex);
             uyb += fe * (r * wq * (3.0 * ey + 9.0 * eu * ey - 3.0 * uy) + k * php * ey);
@@ -219,18 +223,20 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 }
 template <int W>
 __device__ __forceinline__ double lds_ddx(const double* p, int c) {
-    return (4.0 * (p[c + 1] - p[c - 1]) + (p[c + W + 1] - p[c + W - 1]) + (p[c - W + 1] - p[c - W - 1])) / 12.0;
+    return (4.0 * (p[c + 1] - p[c - 1]) + (p[c + W + 1] - p[c + W - 1]) + (p[c - W + 1] - p[c - W - 1])) *
+           (1.0 / 12.0);
 }
 template <int W>
 __device__ __forceinline__ double lds_ddy(const double* p, int c) {
-    return (4.0 * (p[c + W] - p[c - W]) + (p[c + W + 1] + p[c + W - 1]) - (p[c - W - 1] + p[c - W + 1])) / 12.0;
+    return (4.0 * (p[c + W] - p[c - W]) + (p[c + W + 1] + p[c + W - 1]) - (p[c - W - 1] + p[c - W + 1])) *
+           (1.0 / 12.0);
 }
 template <int W>
 __device__ __forceinline__ double lds_lap(const double* p, int c) {
     return (4.0 * (p[c + 1] + p[c - 1] + p[c + W] + p[c - W]) + (p[c + W + 1] + p[c + W - 1] + p[c - W - 1] +
                                                                    p[c - W + 1]) -
-            20.0 * p[c]) /
-           6.0;
+            20.0 * p[c]) *
+           (1.0 / 6.0);
 }
 
 template <typename S>
@@ -325,11 +331,12 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
         Fx = (1.0 / 3.0 - r) * gxv;
         Fy = (1.0 / 3.0 - r) * gyv;
     } else {
-        Fx = lds_ddx<RW>(s_rho, cr) / 3.0 - r * gxv;
-        Fy = lds_ddy<RW>(s_rho, cr) / 3.0 - r * gyv;
+        Fx = lds_ddx<RW>(s_rho, cr) * (1.0 / 3.0) - r * gxv;
+        Fy = lds_ddy<RW>(s_rho, cr) * (1.0 / 3.0) - r * gyv;
     }
-    const double ux = (s_jx[cr] + 0.5 * Fx) / r;
-    const double uy = (s_jy[cr] + 0.5 * Fy) / r;
+    const double ir = 1.0 / r;
+    const double ux = (s_jx[cr] + 0.5 * Fx) * ir;
+    const double uy = (s_jy[cr] + 0.5 * Fy) * ir;
     const double muv = s_mu[cm];
     F(a, RHO)[i] = r;
     F(a, MU)[i] = muv;
@@ -387,16 +394,16 @@ __global__ __launch_bounds__(TX* TY) void adj_back(AdjArgs a, int mode) {
         if (a.improved) {
             const double psixb = -ddx(F(a, DXB), m, nx);
             const double psiyb = -ddy(F(a, DYB), m, nx);
-            const double pm = (a.rec.c0 + F(a, MU)[j]) / 3.0;
-            const double phi = r / 3.0 - pm;
+            const double pm = (a.rec.c0 + F(a, MU)[j]) * (1.0 / 3.0);
+            const double phi = r * (1.0 / 3.0) - pm;
             const double phib = psixb * ux + psiyb * uy;
             uxb += phi * psixb;
             uyb += phi * psiyb;
-            rb += phib / 3.0;
+            rb += phib * (1.0 / 3.0);
             pb -= phib;
-            mub = pb / 3.0;
+            mub = pb * (1.0 / 3.0);
         } else {
-            rb += pb / 3.0;
+            rb += pb * (1.0 / 3.0);
         }
         const double ir = 1.0 / r;
         s_jxb[k] = uxb * ir;
@@ -419,7 +426,7 @@ __global__ __launch_bounds__(TX* TY) void adj_back(AdjArgs a, int mode) {
         const int c = (k / MW + 1) * RW + k % MW + 1;
         s_mub2[k] = s_mub[c] - (lds_ddx<RW>(s_gxb, c) + lds_ddy<RW>(s_gyb, c));
         double rb = s_rb[c];
-        if (!a.improved) rb -= (lds_ddx<RW>(s_fxb, c) + lds_ddy<RW>(s_fyb, c)) / 3.0;
+        if (!a.improved) rb -= (lds_ddx<RW>(s_fxb, c) + lds_ddy<RW>(s_fyb, c)) * (1.0 / 3.0);
         s_rb2[k] = rb;
     }
     __syncthreads();
@@ -510,11 +517,11 @@ __global__ void adj_init_local(AdjArgs a) {
         else pb += (q < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * l;
     }
     if (a.improved) {
-        F(a, PB)[i] = pb / 3.0;   // mu_bar
+        F(a, PB)[i] = pb * (1.0 / 3.0);   // mu_bar
         F(a, RB)[i] = rb;
     } else {
         F(a, PB)[i] = 0.0;
-        F(a, RB)[i] = rb + pb / 3.0;
+        F(a, RB)[i] = rb + pb * (1.0 / 3.0);
     }
 }
 

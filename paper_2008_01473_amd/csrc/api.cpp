@@ -134,11 +134,19 @@ struct lbm_ctx {
     // segment length, the buffer parity and the caller's buffers.
     using SegKey = std::tuple<int, int, const void*, const void*, const void*, const void*, const void*>;
     std::map<SegKey, hipGraphExec_t> seg_graphs;
+    // lbm_adjoint_sweep: recompute (kind 0) and adjoint-step (kind 1) graphs keyed by
+    // (kind, segment length, arena, lam, lam2, ws, grad); a second stream for the
+    // recomputation and the events that order the two streams.
+    std::map<SegKey, hipGraphExec_t> sweep_graphs;
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);   // teardown: nothing to report
         graphs.clear();
         for (auto& kv : seg_graphs) (void)hipGraphExecDestroy(kv.second);
         seg_graphs.clear();
+        for (auto& kv : sweep_graphs) (void)hipGraphExecDestroy(kv.second);
+        sweep_graphs.clear();
     }
 };
 
@@ -456,6 +464,40 @@ int graph_for(lbm_ctx* h, int n, hipGraphExec_t* out) {
     return LBM_OK;
 }
 
+}  // namespace
+
+namespace {
+// Launches of one kind captured once per key and replayed.
+template <class Enqueue>
+int cached_graph(lbm_ctx* h, std::map<lbm_ctx::SegKey, hipGraphExec_t>& cache, const lbm_ctx::SegKey& key,
+                 Enqueue&& enqueue, hipGraphExec_t* out) {
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return LBM_OK;
+    }
+    if (cache.size() >= 16) {                  // callers with fresh buffers every time: keep a few
+        for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+        cache.clear();
+    }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    cache[key] = ex;
+    *out = ex;
+    return LBM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -980,17 +1022,11 @@ namespace {
 // The work of one adjoint segment after its checkpoint has been restored: the
 // recompute of states t0 .. t0 + m - 1 (each kept in `states`) and the adjoint
 // steps back through them.  Leaves h->cur as the recompute leaves it.
-int enqueue_segment(lbm_ctx* h, int m, void* states, double* lam, double* lam2, void* ws, double* grad,
-                    hipStream_t s) {
-    // slot 0 holds the checkpoint; each recompute step writes the next slot, the
-    // last one the handle's current buffer (the handle ends at t0 + m)
+// The adjoint steps of a segment over its states (slots m-1 down to 0 of `states`):
+// on entry lam holds dL/df(t0+m), on exit dL/df(t0).
+int enqueue_adjoint_steps(lbm_ctx* h, int m, void* states, double* lam, double* lam2, void* ws, double* grad,
+                          hipStream_t s) {
     char* st = reinterpret_cast<char*>(states);
-    for (int k = 0; k < m; ++k) {
-        StepArgs a = base_args(h);
-        a.src = st + (size_t)k * h->state_bytes;
-        a.dst = k + 1 < m ? static_cast<void*>(st + (size_t)(k + 1) * h->state_bytes) : h->buf[h->cur];
-        HIP_TRY(launch_step(h, a, kStep, s));
-    }
     double* in = lam;
     double* out = lam2;
     for (int k = m - 1; k >= 0; --k) {
@@ -1003,6 +1039,34 @@ int enqueue_segment(lbm_ctx* h, int m, void* states, double* lam, double* lam2, 
     if (in != lam) HIP_TRY(launch_copy(lam, in, (size_t)9 * h->recs[0].nnodes * sizeof(double), s));
     return LBM_OK;
 }
+
+int enqueue_segment(lbm_ctx* h, int m, void* states, double* lam, double* lam2, void* ws, double* grad,
+                    hipStream_t s) {
+    // slot 0 holds the checkpoint; each recompute step writes the next slot, the
+    // last one the handle's current buffer (the handle ends at t0 + m)
+    char* st = reinterpret_cast<char*>(states);
+    for (int k = 0; k < m; ++k) {
+        StepArgs a = base_args(h);
+        a.src = st + (size_t)k * h->state_bytes;
+        a.dst = k + 1 < m ? static_cast<void*>(st + (size_t)(k + 1) * h->state_bytes) : h->buf[h->cur];
+        HIP_TRY(launch_step(h, a, kStep, s));
+    }
+    return enqueue_adjoint_steps(h, m, states, lam, lam2, ws, grad, s);
+}
+
+// The states a segment's adjoint steps need: slot 0 holds the checkpoint (time
+// level t0), slots 1 .. m-1 receive t0+1 .. t0+m-1.
+int enqueue_recompute(lbm_ctx* h, int m, void* states, hipStream_t s) {
+    char* st = reinterpret_cast<char*>(states);
+    for (int k = 0; k + 1 < m; ++k) {
+        StepArgs a = base_args(h);
+        a.src = st + (size_t)k * h->state_bytes;
+        a.dst = st + (size_t)(k + 1) * h->state_bytes;
+        HIP_TRY(launch_step(h, a, kStep, s));
+    }
+    return LBM_OK;
+}
+
 
 // A segment's launches captured once and replayed (keyed by the buffers, so a
 // caller that keeps its buffers replays one graph per segment).
@@ -1068,6 +1132,85 @@ int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m,
     return LBM_OK;
 }
 
+int lbm_adjoint_sweep(lbm_ctx* h, const void* const* checkpoints, const long long* t0, const int* m, int nseg,
+                      void* states, double* lam, double* lam2, void* ws, double* grad) {
+    int rc = adjoint_check(h);
+    if (rc != LBM_OK) return rc;
+    if (!checkpoints || !t0 || !m || !states || !lam || !lam2 || !ws || !grad) return fail(LBM_ERR_ARG, "null argument");
+    if (nseg < 1) return fail(LBM_ERR_ARG, "nseg must be >= 1");
+    if (lam == lam2) return fail(LBM_ERR_ARG, "lam and lam2 must not alias");
+    if (((uintptr_t)states | (uintptr_t)lam | (uintptr_t)lam2) & 15)
+        return fail(LBM_ERR_ARG, "states, lam and lam2 must be 16-byte aligned");
+    int kmax = 0;
+    for (int i = 0; i < nseg; ++i) {
+        if (!checkpoints[i] || ((uintptr_t)checkpoints[i] & 15))
+            return fail(LBM_ERR_ARG, "every checkpoint must be a 16-byte aligned device pointer");
+        if (m[i] < 1) return fail(LBM_ERR_ARG, "every segment needs m >= 1");
+        if (i > 0 && t0[i] != t0[i - 1] + m[i - 1]) return fail(LBM_ERR_ARG, "segments must be consecutive");
+        kmax = std::max(kmax, m[i]);
+    }
+    rc = reset_status(h);
+    if (rc != LBM_OK) return rc;
+    if (!h->side_stream) HIP_TRY(hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking));
+    for (hipEvent_t& e : h->ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipStream_t A = h->stream, B = h->side_stream;
+    hipEvent_t entry = h->ev[0], rdone[2] = {h->ev[1], h->ev[2]}, adone[2] = {h->ev[3], h->ev[4]};
+    char* arena[2] = {reinterpret_cast<char*>(states), reinterpret_cast<char*>(states) + (size_t)kmax * h->state_bytes};
+    // segment i recomputes into arena i % 2 on B; its adjoint steps run on A
+    auto recompute = [&](int i) -> int {
+        char* st = arena[i % 2];
+        HIP_TRY(launch_copy(st, checkpoints[i], h->state_bytes, B));
+        if (m[i] < 2) return LBM_OK;
+        if (h->use_graphs) {
+            hipGraphExec_t ex = nullptr;
+            const lbm_ctx::SegKey key{0, m[i], st, nullptr, nullptr, nullptr, nullptr};
+            int r = cached_graph(h, h->sweep_graphs, key,
+                                 [&](hipStream_t s) { return enqueue_recompute(h, m[i], st, s); }, &ex);
+            if (r != LBM_OK) return r;
+            HIP_TRY(hipGraphLaunch(ex, B));
+            return LBM_OK;
+        }
+        return enqueue_recompute(h, m[i], st, B);
+    };
+    auto backward = [&](int i) -> int {
+        char* st = arena[i % 2];
+        if (h->use_graphs) {
+            hipGraphExec_t ex = nullptr;
+            const lbm_ctx::SegKey key{1, m[i], st, lam, lam2, ws, grad};
+            int r = cached_graph(
+                h, h->sweep_graphs, key,
+                [&](hipStream_t s) { return enqueue_adjoint_steps(h, m[i], st, lam, lam2, ws, grad, s); }, &ex);
+            if (r != LBM_OK) return r;
+            HIP_TRY(hipGraphLaunch(ex, A));
+            return LBM_OK;
+        }
+        return enqueue_adjoint_steps(h, m[i], st, lam, lam2, ws, grad, A);
+    };
+    // B starts after everything already queued on A (the checkpoints, lam)
+    HIP_TRY(hipEventRecord(entry, A));
+    HIP_TRY(hipStreamWaitEvent(B, entry, 0));
+    rc = recompute(nseg - 1);
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(hipEventRecord(rdone[(nseg - 1) % 2], B));
+    for (int i = nseg - 1; i >= 0; --i) {
+        HIP_TRY(hipStreamWaitEvent(A, rdone[i % 2], 0));
+        if (i > 0) {
+            // segment i-1 reuses the arena of segment i+1, whose adjoint steps must be done
+            if (i + 1 < nseg) HIP_TRY(hipStreamWaitEvent(B, adone[(i + 1) % 2], 0));
+            rc = recompute(i - 1);
+            if (rc != LBM_OK) return rc;
+            HIP_TRY(hipEventRecord(rdone[(i - 1) % 2], B));
+        }
+        rc = backward(i);
+        if (rc != LBM_OK) return rc;
+        HIP_TRY(hipEventRecord(adone[i % 2], A));
+    }
+    h->diag_cache_valid = false;
+    h->t_diag = -1;
+    return LBM_OK;
+}
+
 int lbm_adjoint_fields(lbm_ctx* h, const void* state_t, const double* rho_bar, const double* u_bar, double* lam_out,
                        void* ws, double* grad) {
     int rc = adjoint_check(h);
@@ -1101,6 +1244,9 @@ void lbm_destroy(lbm_ctx* h) {
     if (!h) return;
     h->drop_graphs();
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->side_stream) (void)hipStreamDestroy(h->side_stream);
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
 }
 

@@ -289,6 +289,14 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
     const T phi0 = rho_ref * T(1.0 / 3.0) - pm_ref;      // float32: phi = phi0 + (x - (mu - mu_ref)) / 3
     const MuRef muref(R, F32);
+    // Record fields used in stage D are read here, with the others: a load issued
+    // in stage D would put a memory round trip at the end of every work group.
+    const double rho_max = R.rho_max;
+    const int mrt = MRT ? R.mrt : 0;
+    const T mrt_nu = MRT ? (T)R.nu : T(0);
+    const T mrt_se = MRT ? (T)R.s_e : T(0), mrt_seps = MRT ? (T)R.s_eps : T(0), mrt_sq = MRT ? (T)R.s_q : T(0);
+    const T wall_u0 = PLATES ? (T)R.wall_u0 : T(0), wall_u1 = PLATES ? (T)R.wall_u1 : T(0);
+    const long long field_offset = R.field_offset;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
 
@@ -455,7 +463,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const double m_in = F32 ? mass_in<9, T>(fo) : 0.0;      // exact node mass (float32 storage)
         const int node = gy * nx + gx;
         if constexpr (MODE == kFields) {
-            const long long o = R.field_offset + node;
+            const long long o = field_offset + node;
             if (args.rho_out) args.rho_out[o] = muref.rho_ref + (double)x;
             if (args.mu_out) args.mu_out[o] = mu;
             if (args.u_out) {
@@ -478,15 +486,15 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 dpm = drho * T(1.0 / 3.0);
                 php = T(0);
             }
-            if (MRT && R.mrt) {
+            if (MRT && mrt) {
                 // shear rate: 1/tau, or from the constant kinematic viscosity nu = eta / rho with
                 // eta = p_m (tau_v - 1/2) (improved, Sec. III) or rho/3 (tau_v - 1/2) (standard)
                 T s_v = omega;
-                if (R.nu > 0) {
-                    const T nu = (T)R.nu;
+                if (mrt_nu > T(0)) {
+                    const T nu = mrt_nu;
                     s_v = IMP ? dev_rcp(nu * r * dev_rcp(pm_ref + dpm) + T(0.5)) : dev_rcp(T(3) * nu + T(0.5));
                 }
-                collide_mrt<T>(fo, r, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, (T)R.s_e, (T)R.s_eps, (T)R.s_q, s_v);
+                collide_mrt<T>(fo, r, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, mrt_se, mrt_seps, mrt_sq, s_v);
             } else {
                 collide<T>(fo, r, Sm, ux, uy, Fx, Fy, dpm, php, Cxx, Cyy, omega);
             }
@@ -498,12 +506,12 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
                 // 6 w rho = rho / 6 = p_m / 2; Eq. 27 adds php / 2), and zero on N, S.
                 const T pm = IMP ? pm_ref + dpm : r * T(1.0 / 3.0);
                 if (gy == 0) {
-                    const T w = T(0.5) * pm * (T)R.wall_u0;
+                    const T w = T(0.5) * pm * wall_u0;
                     fo[7] += w;              // SW returns as NE
                     fo[8] -= w;              // SE returns as NW
                 }
                 if (gy == ny - 1) {
-                    const T w = T(0.5) * pm * (T)R.wall_u1;
+                    const T w = T(0.5) * pm * wall_u1;
                     fo[5] -= w;              // NE returns as SW
                     fo[6] += w;              // NW returns as SE
                 }
@@ -522,7 +530,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
         acc.mumin = fmin(acc.mumin, mu);
         acc.mumax = fmax(acc.mumax, mu);
-        acc.status |= blowup_bits<T>(r, ux, uy, T(0), R.rho_max);
+        acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
     }
     }
     if constexpr (MODE == kStep) {

@@ -230,6 +230,11 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const T rho_ref = (T)R.rho_ref, pm_ref = (T)R.pm_ref, mu_ref = (T)R.mu_ref, c0 = (T)R.c0;
     const T phi0 = rho_ref * T(1.0 / 3.0) - pm_ref;      // float32: phi = phi0 + (x - (mu - mu_ref)) / 3
     const MuRef muref(R, F32);
+    // Record fields used in stage D are read here with the others: a load issued in
+    // stage D waits (in issue order) behind every pull before it and puts a memory
+    // round trip into each slice
+    const double rho_max = R.rho_max;
+    const long long field_offset = R.field_offset;
     const int x0 = tile.x0, y0 = tile.y0, z0 = tile.z0, zn = tile.zn;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             const double m_in = F32 ? mass_in<19, T>(f) : 0.0;    // exact node mass (float32 storage)
             const int node = zd * NXY + gy0 * nx + gx0;
             if constexpr (MODE == kFields) {
-                const long long o = R.field_offset + node;
+                const long long o = field_offset + node;
                 if (args.rho_out) args.rho_out[o] = muref.rho_ref + (double)x;
                 if (args.mu_out) args.mu_out[o] = mu;
                 if (args.u_out) {
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
             acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy + uz * uz));
             acc.mumin = fmin(acc.mumin, mu);
             acc.mumax = fmax(acc.mumax, mu);
-            acc.status |= blowup_bits<T>(r, ux, uy, uz, R.rho_max);
+            acc.status |= blowup_bits<T>(r, ux, uy, uz, rho_max);
         }
         __syncthreads();
     };

@@ -162,9 +162,14 @@ def test_adjoint_and_copy_entry_points_reject_before_touching_memory():
     buf = ctypes.cast(fake, ctypes.POINTER(ctypes.c_double))
     assert L.lbm_adjoint_segment(h, fake, 0, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_STATE
     assert L.lbm_adjoint_step(h, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_STATE
+    ck = (ctypes.c_void_p * 2)(fake, fake)
+    t0 = (ctypes.c_longlong * 2)(0, 2)
+    ms = (ctypes.c_int * 2)(2, 2)
+    assert L.lbm_adjoint_sweep(h, ck, t0, ms, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_STATE
     L.lbm_destroy(h)
     rc, h = _create(runtime.params(lattice="D3Q19", nx=8, ny=8, nz=8))
     assert L.lbm_adjoint_segment(h, fake, 0, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_UNSUPPORTED
+    assert L.lbm_adjoint_sweep(h, ck, t0, ms, 2, fake, buf, buf, fake, buf) == lib_mod.LBM_ERR_UNSUPPORTED
     L.lbm_destroy(h)
     assert L.lbm_copy_kernel(ctypes.c_void_p(0x1004), fake, 64, None) == lib_mod.LBM_ERR_ARG
     assert L.lbm_copy_kernel(None, fake, 64, None) == lib_mod.LBM_ERR_ARG

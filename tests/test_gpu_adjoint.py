@@ -1,6 +1,7 @@
 """Hand-written adjoint on the GPU vs autograd of the float64 CPU oracle, vs central
 finite differences of the GPU forward, and the dot-product identity."""
 
+import ctypes
 import math
 
 import numpy as np
@@ -325,5 +326,59 @@ def test_adjoint_segment_equals_step_by_step(m, graphs):
         assert torch.equal(lam_b, lam)
         assert torch.equal(g1, g2)
         assert sim.time == t0 + m
+        assert torch.equal(sim.get_state()[0], end_state)
+    roll.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_adjoint_sweep_equals_segment_by_segment(graphs):
+    """lbm_adjoint_sweep (every segment in one call, the recomputation of segment i
+    on a second stream overlapping the adjoint steps of segment i+1, two arenas)
+    gives the lambda and parameter gradients of lbm_adjoint_segment called segment
+    by segment in reverse, bit for bit: three segments of 4, 4 and 3 steps, eager
+    and from captured graphs, twice on the same buffers (the second call replays),
+    and leaves the handle's state and time level unchanged."""
+    p, rho0 = _case("improved")
+    roll = Rollout(p)
+    sim = roll.sim
+    sim.use_graphs(graphs)
+    L = _lib.lib()
+    sim.init(rho0)
+    ms = [4, 4, 3]
+    t0s, cks = [], []
+    for m in ms:
+        ck, t = sim.get_state()
+        t0s.append(t)
+        cks.append(ck.clone())
+        sim.step(m)
+    end_state, t_end = sim.get_state()
+    end_state = end_state.clone()
+    lam0 = torch.randn(9 * sim.N, dtype=torch.float64, generator=torch.Generator().manual_seed(7)).cuda()
+    # segment by segment
+    states = torch.empty(max(ms) * sim.state_bytes, dtype=torch.uint8, device="cuda")
+    lam, lam2 = lam0.clone(), torch.empty_like(lam0)
+    g1 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for ck, t0, m in reversed(list(zip(cks, t0s, ms))):
+        _lib.check(L.lbm_adjoint_segment(sim.h, ck.data_ptr(), t0, m, states.data_ptr(), lam.data_ptr(),
+                                         lam2.data_ptr(), roll.ws.data_ptr(), g1.data_ptr()))
+    torch.cuda.synchronize()
+    sim.set_state(end_state, t_end)
+    # one sweep call, twice on the same buffers
+    arenas = torch.empty(2 * max(ms) * sim.state_bytes, dtype=torch.uint8, device="cuda")
+    lam_b, lam_b2 = torch.empty_like(lam0), torch.empty_like(lam0)
+    g2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    n = len(ms)
+    ptrs = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cks])
+    for rep in range(2):
+        print(f"case adjoint sweep graphs={graphs} call {rep}", flush=True)
+        lam_b.copy_(lam0)
+        g2.zero_()
+        _lib.check(L.lbm_adjoint_sweep(sim.h, ptrs, (ctypes.c_longlong * n)(*t0s), (ctypes.c_int * n)(*ms), n,
+                                       arenas.data_ptr(), lam_b.data_ptr(), lam_b2.data_ptr(), roll.ws.data_ptr(),
+                                       g2.data_ptr()))
+        torch.cuda.synchronize()
+        assert torch.equal(lam_b, lam)
+        assert torch.equal(g1, g2)
+        assert sim.time == t_end
         assert torch.equal(sim.get_state()[0], end_state)
     roll.close()
