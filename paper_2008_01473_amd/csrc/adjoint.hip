@@ -158,45 +158,51 @@ __global__ void fwd_mu(AdjArgs a, int from_rho0) {
 // A1: local adjoint of the collision at node i; lam[q] = lam_in(x + e_q).
 __device__ __forceinline__ void collision_vjp(const AdjArgs& a, int i, const double (&lam)[9], double r, double ux,
                                               double uy, double Fx, double Fy, double mu) {
+    // Every partial below is linear in lam with coefficients polynomial in e_q, so
+    // it is assembled from a few moments of lam (q != 0 unless stated):
+    //   W0 = sum w_q lam_q, W1 = sum w_q lam_q e_q, W2 = sum w_q lam_q e_q e_q^T,
+    //   K1 = sum k_q lam_q e_q (k_q: coefficient of php (e.u) in the equilibrium,
+    //   -1/2 on the axes, 1/4 on the diagonals), Cs = sum c_q lam_q (c_q: coefficient
+    //   of p_m, 1/3 and 1/12), V0 = W0 + w_0 lam_0 (Guo forcing covers q = 0 too), and
+    //   CX, CY = sum over all q of lam_q times the C_xx, C_yy coefficients of C_q.
+    // Equilibrium (closed form of M^-1 Eq. 27): rest rho - 5 p_m/3 - (2/3) rho u^2;
+    //   others c_q p_m + rho w_q (3 e.u + 4.5 (e.u)^2 - 1.5 u^2) + k_q php e.u.
+    // Guo forcing (Eq. 14): w_q [3 (e - u).F + 9 (e.u)(e.F)].
     const double w = a.rec.omega, w2 = 1.0 - 0.5 * w;
     const double pm = a.improved ? (a.rec.c0 + mu) * (1.0 / 3.0) : r * (1.0 / 3.0);
     const double php = pm - r * (1.0 / 3.0);
     const double usq = ux * ux + uy * uy;
-    double rb = 0, uxb = 0, uyb = 0, pb = 0, fxb = 0, fyb = 0, cxxb = 0, cyyb = 0;
-    for (int q = 0; q < 9; ++q) {
-        const double ab = lam[q];
-        const double ex = EX[q], ey = EY[q];
-        const double eu = ex * ux + ey * uy, eF = ex * Fx + ey * Fy;
-        const double fe = w * ab, gb = w2 * ab;
-        // equilibrium partials (closed form of M^-1 Eq. 27)
-        if (q == 0) {
-            rb += fe * (1.0 - (2.0 / 3.0) * usq);
-            pb += fe * (-5.0 / 3.0);
-            uxb += fe * (-(4.0 / 3.0) * r * ux);
-            uyb += fe * (-(4.0 / 3.0) * r * uy);
-        } else {
-            const double wq = W[q];
-            const double k = (q < 5) ? -0.5 : 0.25;             // coefficient of php * eu
-            rb += fe * (wq * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq) - k * eu * (1.0 / 3.0));
-            pb += fe * ((q < 5 ? 1.0 / 3.0 : 1.0 / 12.0) + k * eu);
-            uxb += fe * (r * wq * (3.0 * ex + 9.0 * eu * ex - 3.0 * ux) + k * php * ex);
-            uyb += fe * (r * wq * (3.0 * ey + 9.0 * eu * ey - 3.0 * uy) + k * php * ey);
-        }
-        // Guo forcing G = w [3 (e - u).F + 9 (e.u)(e.F)]
-        uxb += gb * W[q] * (-3.0 * Fx + 9.0 * ex * eF);
-        uyb += gb * W[q] * (-3.0 * Fy + 9.0 * ey * eF);
-        fxb += gb * W[q] * (3.0 * (ex - ux) + 9.0 * eu * ex);
-        fyb += gb * W[q] * (3.0 * (ey - uy) + 9.0 * eu * ey);
-        // correction C (linear in C_xx, C_yy)
-        if (a.improved) {
-            double cx, cy;
-            if (q == 0) { cx = -1.0 / 3.0; cy = -1.0 / 3.0; }
-            else if (q == 1 || q == 3) { cx = 1.0 / 6.0; cy = -1.0 / 3.0; }
-            else if (q == 2 || q == 4) { cx = -1.0 / 3.0; cy = 1.0 / 6.0; }
-            else { cx = 1.0 / 6.0; cy = 1.0 / 6.0; }
-            cxxb += gb * cx;
-            cyyb += gb * cy;
-        }
+    const double ax = lam[1] + lam[3], ay = lam[2] + lam[4];            // axis pairs
+    const double dxa = lam[1] - lam[3], dya = lam[2] - lam[4];
+    const double dg = (lam[5] + lam[7]) + (lam[6] + lam[8]);            // diagonals
+    const double dgx = (lam[5] - lam[7]) + (lam[8] - lam[6]);           // sum e_x lam over diagonals
+    const double dgy = (lam[5] - lam[7]) + (lam[6] - lam[8]);           // sum e_y lam over diagonals
+    const double dgxy = (lam[5] + lam[7]) - (lam[6] + lam[8]);          // sum e_x e_y lam
+    const double W0 = (ax + ay) * (1.0 / 9.0) + dg * (1.0 / 36.0);
+    const double W1x = dxa * (1.0 / 9.0) + dgx * (1.0 / 36.0), W1y = dya * (1.0 / 9.0) + dgy * (1.0 / 36.0);
+    const double Wxx = ax * (1.0 / 9.0) + dg * (1.0 / 36.0), Wyy = ay * (1.0 / 9.0) + dg * (1.0 / 36.0);
+    const double Wxy = dgxy * (1.0 / 36.0);
+    const double K1x = -0.5 * dxa + 0.25 * dgx, K1y = -0.5 * dya + 0.25 * dgy;
+    const double Cs = (ax + ay) * (1.0 / 3.0) + dg * (1.0 / 12.0);
+    const double V0 = W0 + (4.0 / 9.0) * lam[0];
+    const double l0 = lam[0];
+    const double uK = ux * K1x + uy * K1y;
+    const double W2ux = Wxx * ux + Wxy * uy, W2uy = Wxy * ux + Wyy * uy;      // W2 u
+    const double W2Fx = Wxx * Fx + Wxy * Fy, W2Fy = Wxy * Fx + Wyy * Fy;      // W2 F
+    const double rb = w * (l0 * (1.0 - (2.0 / 3.0) * usq) + 3.0 * (ux * W1x + uy * W1y) +
+                           4.5 * (ux * W2ux + uy * W2uy) - 1.5 * usq * W0 - uK * (1.0 / 3.0));
+    const double pb = w * (-(5.0 / 3.0) * l0 + Cs + uK);
+    const double uxb = w * (-(4.0 / 3.0) * r * ux * l0 + r * (3.0 * W1x + 9.0 * W2ux - 3.0 * ux * W0) + php * K1x) +
+                       w2 * (-3.0 * Fx * V0 + 9.0 * W2Fx);
+    const double uyb = w * (-(4.0 / 3.0) * r * uy * l0 + r * (3.0 * W1y + 9.0 * W2uy - 3.0 * uy * W0) + php * K1y) +
+                       w2 * (-3.0 * Fy * V0 + 9.0 * W2Fy);
+    const double fxb = w2 * (3.0 * W1x - 3.0 * ux * V0 + 9.0 * W2ux);
+    const double fyb = w2 * (3.0 * W1y - 3.0 * uy * V0 + 9.0 * W2uy);
+    double cxxb = 0.0, cyyb = 0.0;
+    if (a.improved) {
+        // C_q coefficients (C_xx, C_yy): rest (-1/3, -1/3); +-x (1/6, -1/3); +-y (-1/3, 1/6); diagonals (1/6, 1/6)
+        cxxb = w2 * (-(1.0 / 3.0) * l0 + (1.0 / 6.0) * ax - (1.0 / 3.0) * ay + (1.0 / 6.0) * dg);
+        cyyb = w2 * (-(1.0 / 3.0) * l0 - (1.0 / 3.0) * ax + (1.0 / 6.0) * ay + (1.0 / 6.0) * dg);
     }
     F(a, RB)[i] = rb;
     F(a, UXB)[i] = uxb;
@@ -214,6 +220,9 @@ __device__ __forceinline__ void collision_vjp(const AdjArgs& a, int i, const dou
 // fwd_moments, fwd_mu, fwd_force and adj_local, which it replaces in the step and
 // fields modes).
 constexpr int TX = 32, TY = 8;
+// Threads per work group: twice the tile, so that the ring stages (tile + 2: 432
+// nodes, tile + 1: 340) take one pass each; the tile's own nodes use the first half.
+constexpr int NTH = 2 * TX * TY;
 constexpr int RW = TX + 4, RH = TY + 4;      // rho, j: tile + 2
 constexpr int MW = TX + 2, MH = TY + 2;      // mu: tile + 1
 
@@ -240,7 +249,7 @@ __device__ __forceinline__ double lds_lap(const double* p, int c) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) {
+__global__ __launch_bounds__(NTH) void adj_front(AdjArgs a, int fields_mode) {
     __shared__ double s_rho[RH * RW], s_jx[RH * RW], s_jy[RH * RW];
     __shared__ double s_mu[MH * MW];
     const int nx = a.nx, ny = a.ny;
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
     }
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
-    const bool own = gx < nx && gy < ny;
+    const bool own = tid < TX * TY && gx < nx && gy < ny;
     const int i = own ? gy * nx + gx : 0;
     const Nbr n = nbr(i, nx, ny);
     // the cotangents gathered by the collision adjoint, lam(x + e_q), are loaded
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
     }
     // rho and j on the tile + 2 rings (periodic): both of a thread's nodes' pulls
     // are issued before either is summed
-    constexpr int NT = TX * TY, NR = (RH * RW + NT - 1) / NT;
+    constexpr int NT = NTH, NR = (RH * RW + NT - 1) / NT;
     double fr[NR][9];
 #pragma unroll
     for (int h = 0; h < NR; ++h) {
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
     }
     __syncthreads();
     // mu on the tile + 1 ring; L, dmu/drho and dmu/d(T/Tc) of the tile's nodes
-    for (int k = tid; k < MH * MW; k += TX * TY) {
+    for (int k = tid; k < MH * MW; k += NTH) {
         const int mx = k % MW, my = k / MW;
         const int c = (my + 1) * RW + mx + 1;
         double mu, dr, dt;
@@ -363,8 +372,8 @@ __global__ __launch_bounds__(TX* TY) void adj_front(AdjArgs a, int fields_mode) 
 // mu_bar -= div(g_bar) (standard force: rho_bar -= div(F_bar)/3), and on the tile
 // rho_bar through mu, the parameter partials and dL/df(t).  The same formulas,
 // in the same order, as the per-node kernels they replaced.
-__global__ __launch_bounds__(TX* TY) void adj_back(AdjArgs a, int mode) {
-    constexpr int NT = TX * TY, VN = RH * RW, MN = MH * MW;
+__global__ __launch_bounds__(NTH) void adj_back(AdjArgs a, int mode) {
+    constexpr int NT = NTH, VN = RH * RW, MN = MH * MW;
     __shared__ double s_gxb[VN], s_gyb[VN], s_fxb[VN], s_fyb[VN], s_rb[VN], s_mub[VN], s_jxb[VN], s_jyb[VN];
     __shared__ double s_mub2[MN], s_rb2[MN];
     __shared__ double sk[NT], st[NT];
@@ -374,7 +383,7 @@ __global__ __launch_bounds__(TX* TY) void adj_back(AdjArgs a, int mode) {
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int gx = x0 + lx, gy = y0 + ly;
-    const bool own = gx < nx && gy < ny;
+    const bool own = tid < TX * TY && gx < nx && gy < ny;
     const int i = own ? gy * nx + gx : 0;
     const Nbr n = nbr(i, nx, ny);
     double lam[9];
@@ -625,10 +634,10 @@ hipError_t adjoint_launch(int kind, const LatticeRec& rec, double dRT, int preci
     const int tiles = ((a.nx + adj::TX - 1) / adj::TX) * ((a.ny + adj::TY - 1) / adj::TY);
     a.pending = (chain & kAdjPending) ? tiles : 0;
     if (precision == 0)
-        hipLaunchKernelGGL(adj::adj_front<double>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
+        hipLaunchKernelGGL(adj::adj_front<double>, dim3(tiles), dim3(adj::NTH), 0, s, a, kind == 1 ? 1 : 0);
     else
-        hipLaunchKernelGGL(adj::adj_front<float>, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
-    hipLaunchKernelGGL(adj::adj_back, dim3(tiles), dim3(adj::TX * adj::TY), 0, s, a, kind == 1 ? 1 : 0);
+        hipLaunchKernelGGL(adj::adj_front<float>, dim3(tiles), dim3(adj::NTH), 0, s, a, kind == 1 ? 1 : 0);
+    hipLaunchKernelGGL(adj::adj_back, dim3(tiles), dim3(adj::NTH), 0, s, a, kind == 1 ? 1 : 0);
     if (!(chain & kAdjDeferReduce))
         hipLaunchKernelGGL(adj::adj_reduce, dim3(1), dim3(64), 0, s, a.partial, tiles, grad);
     return hipGetLastError();
