@@ -71,6 +71,17 @@ __device__ __forceinline__ double* F(const AdjArgs& a, int k) { return a.ws + (s
 struct Nbr {
     int xm, xp, ym, yp, x, y;
 };
+// Neighbours of node (x, y), 0 <= x < nx, 0 <= y < ny (periodic).
+__device__ __forceinline__ Nbr nbr_xy(int x, int y, int nx, int ny) {
+    Nbr n;
+    n.x = x;
+    n.y = y;
+    n.xm = x == 0 ? nx - 1 : x - 1;
+    n.xp = x == nx - 1 ? 0 : x + 1;
+    n.ym = y == 0 ? ny - 1 : y - 1;
+    n.yp = y == ny - 1 ? 0 : y + 1;
+    return n;
+}
 __device__ __forceinline__ Nbr nbr(int i, int nx, int ny) {
     Nbr n;
     n.x = i % nx;
@@ -227,6 +238,11 @@ constexpr int RW = TX + 4, RH = TY + 4;      // rho, j: tile + 2
 constexpr int MW = TX + 2, MH = TY + 2;      // mu: tile + 1
 
 __device__ __forceinline__ int wrapn(int v, int n) {
+    // one period off in either direction needs no division; lattices narrower than
+    // the tile's halo take the remainder
+    v += v < 0 ? n : 0;
+    v -= v >= n ? n : 0;
+    if ((unsigned)v < (unsigned)n) return v;
     const int r = v % n;
     return r < 0 ? r + n : r;
 }
@@ -276,7 +292,7 @@ __global__ __launch_bounds__(NTH) void adj_front(AdjArgs a, int fields_mode) {
     const int gx = x0 + lx, gy = y0 + ly;
     const bool own = tid < TX * TY && gx < nx && gy < ny;
     const int i = own ? gy * nx + gx : 0;
-    const Nbr n = nbr(i, nx, ny);
+    const Nbr n = own ? nbr_xy(gx, gy, nx, ny) : nbr_xy(0, 0, nx, ny);
     // the cotangents gathered by the collision adjoint, lam(x + e_q), are loaded
     // first so that their latency overlaps the stages below
     double lam[9];
@@ -385,7 +401,7 @@ __global__ __launch_bounds__(NTH) void adj_back(AdjArgs a, int mode) {
     const int gx = x0 + lx, gy = y0 + ly;
     const bool own = tid < TX * TY && gx < nx && gy < ny;
     const int i = own ? gy * nx + gx : 0;
-    const Nbr n = nbr(i, nx, ny);
+    const Nbr n = own ? nbr_xy(gx, gy, nx, ny) : nbr_xy(0, 0, nx, ny);
     double lam[9];
     if (own && mode == 0) {
 #pragma unroll
@@ -395,7 +411,7 @@ __global__ __launch_bounds__(NTH) void adj_back(AdjArgs a, int mode) {
     for (int k = tid; k < VN; k += NT) {
         const int x = wrapn(x0 - 2 + k % RW, nx), y = wrapn(y0 - 2 + k / RW, ny);
         const int j = y * nx + x;
-        const Nbr m = nbr(j, nx, ny);
+        const Nbr m = nbr_xy(x, y, nx, ny);
         const double r = F(a, RHO)[j], ux = F(a, UX)[j], uy = F(a, UY)[j];
         double rb = F(a, RB)[j], uxb = F(a, UXB)[j], uyb = F(a, UYB)[j], pb = F(a, PB)[j];
         double fxb = F(a, FXB)[j], fyb = F(a, FYB)[j];
