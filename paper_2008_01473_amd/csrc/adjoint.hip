@@ -118,17 +118,17 @@ __device__ __forceinline__ double lap(const double* p, const Nbr& n, int nx) {
 __device__ __forceinline__ void eos_terms(const LatticeRec& R, double dRT, double rho, double& mu,
                                           double& dmu_drho, double& dmu_dt) {
     const double RT = R.RT, a = R.a, b = R.b;
-    // one reciprocal of (1 - b rho) or (1 - h) and one of rho; the kernels' float64
-    // logarithm (log_pos)
-    const double ir = 1.0 / rho;
+    // one reciprocal of (1 - b rho) or (1 - h) and one of rho (rcp_nr); the
+    // kernels' float64 logarithm (log_pos)
+    const double ir = rcp_nr(rho);
     if (R.eos == 0) {
-        const double ibr = 1.0 / (1.0 - b * rho);
+        const double ibr = rcp_nr(1.0 - b * rho);
         const double s = log_pos(rho * ibr) + ibr;
         mu = RT * s - 2.0 * a * rho;
         dmu_drho = RT * ir * (ibr * ibr) - 2.0 * a;
         dmu_dt = dRT * s;
     } else {
-        const double h = 0.25 * b * rho, iom = 1.0 / (1.0 - h);
+        const double h = 0.25 * b * rho, iom = rcp_nr(1.0 - h);
         const double iom3 = iom * iom * iom;
         const double s = log_pos(rho) + 1.0 + h * (8.0 - 9.0 * h + 3.0 * h * h) * iom3;
         mu = RT * s - 2.0 * a * rho;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NTH) void adj_front(AdjArgs a, int fields_mode) {
         Fx = lds_ddx<RW>(s_rho, cr) * (1.0 / 3.0) - r * gxv;
         Fy = lds_ddy<RW>(s_rho, cr) * (1.0 / 3.0) - r * gyv;
     }
-    const double ir = 1.0 / r;
+    const double ir = rcp_nr(r);
     const double ux = (s_jx[cr] + 0.5 * Fx) * ir;
     const double uy = (s_jy[cr] + 0.5 * Fy) * ir;
     const double muv = s_mu[cm];
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(NTH) void adj_back(AdjArgs a, int mode) {
         } else {
             rb += pb * (1.0 / 3.0);
         }
-        const double ir = 1.0 / r;
+        const double ir = rcp_nr(r);
         s_jxb[k] = uxb * ir;
         s_jyb[k] = uyb * ir;
         fxb += 0.5 * uxb * ir;

@@ -14,12 +14,24 @@ __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ bool dev_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool dev_finite(double x) { return isfinite(x); }
 
+// Reciprocal of a finite non-zero float64 value: the hardware approximation refined
+// by two Newton-Raphson steps r <- r + r (1 - x r), each doubling the correct bits;
+// within about 1 ulp, without the scaling and fix-up steps of a correctly rounded
+// division (zero or non-finite x give NaN, which the blow-up flags catch).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Natural logarithm of a float64 argument by range reduction and the atanh series:
 // x = 2^e m with m in [sqrt(1/2), sqrt(2)), and log m = 2 atanh(s) with
 // s = (m - 1)/(m + 1), summed as 2 s (1 + s^2/3 + s^4/5 + ... + s^22/23)
 // (|s| <= 0.1716: truncation below 1e-18 relative); e ln 2 is added with ln 2 split
-// into a 29-bit head (exact products with e) and the tail.  Within 2 ulp of the
-// exact logarithm (checked against 60-digit arithmetic over 1e-6 .. 1e6); zero,
+// into a 29-bit head (exact products with e) and the tail; s takes the reciprocal
+// of (2 + f) above.  Within a few ulp of the exact logarithm; zero,
 // negative and non-finite arguments give what the C library's log gives.  The
 // equation of state only takes logarithms of finite positive densities, so this
 // skips the general routine's extra-precision and special-case work (about a
@@ -33,7 +45,7 @@ __device__ __forceinline__ double log_pos(double x) {
         --e;
     }
     const double f = m - 1.0;                    // exact
-    const double s = f / (2.0 + f);
+    const double s = f * rcp_nr(2.0 + f);
     const double z = s * s;
     double p = 1.0 / 23.0;
     p = fma(p, z, 1.0 / 21.0);
@@ -54,9 +66,9 @@ __device__ __forceinline__ double log_pos(double x) {
     return x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan(""));
 }
 
-// Reciprocal and logarithm on the step's critical path: in float64 the IEEE
-// reciprocal and log_pos above; in float32 the hardware 1-ulp instructions.
-__device__ __forceinline__ double dev_rcp(double x) { return 1.0 / x; }
+// Reciprocal and logarithm on the step's critical path: in float64 rcp_nr and
+// log_pos above; in float32 the hardware 1-ulp instructions.
+__device__ __forceinline__ double dev_rcp(double x) { return rcp_nr(x); }
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double dev_logf(double x) { return log_pos(x); }
 __device__ __forceinline__ float dev_logf(float x) { return __logf(x); }
