@@ -341,8 +341,11 @@ double lbm_critical_temperature(int eos, double a, double b, double R);
  * [0, lbm_num_tile_shapes) names the output tile of one work group, bx x by
  * nodes; for D3Q19 it also fixes the z-chunk bz each work group sweeps (the same
  * xy tile appears with several chunk lengths).  lbm_describe_tile_shape reports
- * (bx, by, bz); for D2Q9, bz is the number of nodes each thread owns (1 or 2,
- * rows by / bz apart; work groups of bx * by / bz threads).  The 2048-node D2Q9
+ * (bx, by, bz); for D2Q9, bz > 0 is the number of nodes each thread owns (1 or
+ * 2, rows by / bz apart; work groups of bx * by / bz threads), and bz = -2 marks
+ * work groups of 2 * bx * by threads, one owning each node and the others taking
+ * halo pulls and a share of the ring stages (shorter stages for lattices that fill
+ * the chip with a single wave of work groups).  The 2048-node D2Q9
  * tile exists in float32 only; it and some D3Q19 float64 shapes return
  * LBM_ERR_UNSUPPORTED in float64 (LDS), and lbm_autotune skips them.  Re-tiling
  * synchronises the handle's stream. */

@@ -227,9 +227,13 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 // diagnostics, or writing rho, u, mu of the current time level.
 // FEAT bit 1: lattices of the launch may use the MRT collision; bit 2: they may
 // have plates (the lattice record decides); launches without them carry no such code.
-template <typename S, typename T, int V, int BX, int BY, int MODE, int FEAT, int NPT>
-__global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
-    constexpr int NT = BX * BY;
+// XT: work-group threads per own thread.  With XT = 2 the second half of the work
+// group owns no node: it takes the halo pulls of stage A, and every thread takes a
+// share of stages B and C, so that each stage is one pass over the tile's rings.
+template <typename S, typename T, int V, int BX, int BY, int MODE, int FEAT, int NPT, int XT = 1>
+__global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
+    constexpr int NT = BX * BY;                    // threads that own nodes
+    constexpr int TPB = NT * XT;                   // threads of the work group
     constexpr int TH = BY * NPT, NN = BX * TH;     // tile: BX x TH nodes, NPT per thread (rows BY apart)
     constexpr bool MRT = (FEAT & 1) != 0;
     constexpr bool PLATES = (FEAT & 2) != 0;
@@ -242,8 +246,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     __shared__ T s_b[H1 * W1];            // j_y, then psi_y
     __shared__ T s_F[2 * NN], s_u[2 * NN];
     __shared__ T s_P[PT ? 3 * H2 * W2 : 1];
-    __shared__ double s_red[7 * (NT / 64)];
-    __shared__ unsigned s_ured[NT / 64];
+    __shared__ double s_red[7 * (TPB / 64)];
+    __shared__ unsigned s_ured[TPB / 64];
 
     const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
     if (t_idx >= args.ntiles) return;
@@ -299,12 +303,16 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     const long long field_offset = R.field_offset;
     const int tid = threadIdx.x;
     const int lx0 = tid % BX, ly0 = tid / BX;
+    const bool owner = XT == 1 || tid < NT;
+    // halo slot of this thread: helper threads first, then the owners
+    const int hslot = XT == 1 ? tid : (tid >= NT ? tid - NT : tid + (TPB - NT));
+    const int hwave = XT == 1 ? (tid & ~63) : ((tid & ~63) >= NT ? (tid & ~63) - NT : (tid & ~63) + (TPB - NT));
 
     // ---- stage A: the interior node owned by this thread (kept in registers for
     // stage D) and up to HP nodes of the three halo rings; every load is issued
     // before any is used.
     constexpr int HALO = H3 * W3 - NN;
-    constexpr int HP = (HALO + NT - 1) / NT;
+    constexpr int HP = (HALO + TPB - 1) / TPB;
     T fown[NPT][9];
     T fh[HP][9];
     int hpos[HP];
@@ -318,9 +326,10 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     bool h_mirror[HP];
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
+        own_mirror[p] = false;
+        if (!owner) continue;
         const int gx = x0 + lx0, gy = y0 + ly0 + p * BY;
         const int xc = wx(gx), xm = wx(gx - 1), xp = wx(gx + 1);
-        own_mirror[p] = false;
         if (plates) {
             pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, own_mirror[p]), fown[p]);
         } else {
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     }
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
-        int k = tid + q * NT;
+        int k = hslot + q * TPB;
         k = k < HALO ? k : HALO - 1;          // idle lanes repeat the last halo node
         int lx, ly;
         if (k < 3 * W3) {
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         const int xc = wx(gx), xm = wx(gx - 1), xp = wx(gx + 1);
         h_mirror[q] = false;
-        if ((tid & ~63) + q * NT < HALO) {            // waves with no halo node left skip the pulls
+        if (hwave + q * TPB < HALO) {                 // waves with no halo node left skip the pulls
             if (plates) {
                 pull_plates<S, T>(pp, nx, ny, xm, xc, xp, plate_row(gy, ny, h_mirror[q]), fh[q]);
             } else {
@@ -366,6 +375,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     // a mirror image beyond a plate carries the reflected momentum (j_y negated)
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
+        if (!owner) continue;
         const int ly = ly0 + p * BY;
         s_rho[(ly + 3) * W3 + lx0 + 3] = sum9(fown[p]);
         s_a[(ly + 1) * W1 + lx0 + 1] = jx9(fown[p]);
@@ -373,7 +383,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     }
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
-        if (tid + q * NT < HALO) {
+        if (hslot + q * TPB < HALO) {
             const int pos = hpos[q];
             const int ly = pos / W3, lx = pos - ly * W3;
             s_rho[pos] = sum9(fh[q]);
@@ -387,7 +397,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     if (s_skip != 0u) return;
 
     // ---- stage B: chemical potential (and pressure tensor) on tile + 2 ----
-    for (int k = tid; k < H2 * W2; k += NT) {
+    for (int k = tid; k < H2 * W2; k += TPB) {
         const int lx = k % W2, ly = k / W2;
         const int c = (ly + 1) * W3 + lx + 1;
         const T x = s_rho[c];
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     __syncthreads();
 
     // ---- stage C: force, velocity, psi on tile + 1 ----
-    for (int k = tid; k < H1 * W1; k += NT) {
+    for (int k = tid; k < H1 * W1; k += TPB) {
         const int lx = k % W1, ly = k / W1;
         const int c2 = (ly + 1) * W2 + lx + 1;
         const int c3 = (ly + 2) * W3 + lx + 2;
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     T (&fo)[9] = fown[p];
     const int ly = ly0 + p * BY, io = tid + p * NT;
     const int gx = x0 + lx0, gy = y0 + ly;
-    if (gx < nx && gy < ny) {
+    if (owner && gx < nx && gy < ny) {
         const int c3 = (ly + 3) * W3 + lx0 + 3, c2 = (ly + 2) * W2 + lx0 + 2, c1 = (ly + 1) * W1 + lx0 + 1;
         const T x = s_rho[c3];
         const T r = rho_ref + x;
@@ -536,7 +546,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + lat, acc.status);
     } else {
-        block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+        block_reduce_store<TPB>(acc, args.partial + t_idx, s_red, s_ured);
         if (threadIdx.x == 0) {
             const unsigned st = args.partial[t_idx].status;
             if (st) atomicOr(args.status + lat, st);
@@ -633,38 +643,38 @@ __global__ void convert_kernel(S* state, const LatticeRec* recs, int nlat, doubl
 // Host-side launchers (called by the runtime).
 
 namespace {
-template <typename S, typename T, int V, int BX, int BY, int MODE, int NPT>
+template <typename S, typename T, int V, int BX, int BY, int MODE, int NPT, int XT>
 void launch_feat(const StepArgs& a, int feat, dim3 g, dim3 b, hipStream_t s) {
     switch (feat) {
-        case 1: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 1, NPT>), g, b, 0, s, a); return;
+        case 1: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 1, NPT, XT>), g, b, 0, s, a); return;
         case 2:
             if constexpr (V != kStdPtensor)      // plates are not offered with the pressure-tensor force
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 2, NPT>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 2, NPT, XT>), g, b, 0, s, a);
             return;
         case 3:
             if constexpr (V != kStdPtensor)
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 3, NPT>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 3, NPT, XT>), g, b, 0, s, a);
             return;
-        default: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 0, NPT>), g, b, 0, s, a); return;
+        default: hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, MODE, 0, NPT, XT>), g, b, 0, s, a); return;
     }
 }
 
-template <typename S, typename T, int V, int BX, int BY, int NPT = 1>
+template <typename S, typename T, int V, int BX, int BY, int NPT = 1, int XT = 1>
 hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
-    const dim3 g(grid), b(BX * BY);
+    const dim3 g(grid), b(BX * BY * XT);
     const int feat = (a.any_mrt ? 1 : 0) | (a.any_plates ? 2 : 0);
     if (mode == kFields) {
         if constexpr (V != kStdPtensor) {
             if (a.any_plates) {
-                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 2, NPT>), g, b, 0, s, a);
+                hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 2, NPT, XT>), g, b, 0, s, a);
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0, NPT>), g, b, 0, s, a);
+        hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0, NPT, XT>), g, b, 0, s, a);
     } else if (mode == kStepDiag) {
-        launch_feat<S, T, V, BX, BY, kStepDiag, NPT>(a, feat, g, b, s);
+        launch_feat<S, T, V, BX, BY, kStepDiag, NPT, XT>(a, feat, g, b, s);
     } else {
-        launch_feat<S, T, V, BX, BY, kStep, NPT>(a, feat, g, b, s);
+        launch_feat<S, T, V, BX, BY, kStep, NPT, XT>(a, feat, g, b, s);
     }
     return hipGetLastError();
 }
@@ -682,17 +692,24 @@ hipError_t launch_shape(const StepArgs& a, int grid, hipStream_t s, int fields, 
             if constexpr (sizeof(S) == 4) return launch_step_t<S, T, V, 128, 8, 2>(a, grid, s, fields);
             return hipErrorInvalidValue;
         case 7: return launch_step_t<S, T, V, 64, 8, 2>(a, grid, s, fields);     // 64 x 16 nodes, two per thread
+        case 8: return launch_step_t<S, T, V, 32, 16, 1, 2>(a, grid, s, fields);   // 32 x 16 nodes, 1024 threads
+        case 9: return launch_step_t<S, T, V, 32, 8, 1, 2>(a, grid, s, fields);    // 32 x 8 nodes, 512 threads
+        case 10: return launch_step_t<S, T, V, 64, 8, 1, 2>(a, grid, s, fields);   // 64 x 8 nodes, 1024 threads
+        case 11: return launch_step_t<S, T, V, 16, 16, 1, 2>(a, grid, s, fields);  // 16 x 16 nodes, 512 threads
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
 extern const int kD2Q9Shapes[][2];
-const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}, {128, 16}, {64, 16}};
+const int kD2Q9Shapes[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 16}, {128, 8}, {128, 16}, {64, 16},
+                              {32, 16}, {32, 8}, {64, 8}, {16, 16}};
 extern const int kNumD2Q9Shapes;
-const int kNumD2Q9Shapes = 8;
-extern const int kD2Q9NodesPerThread[];          // rows a thread owns, by / nodes-per-thread apart
-const int kD2Q9NodesPerThread[] = {1, 1, 1, 1, 1, 1, 2, 2};
+const int kNumD2Q9Shapes = 12;
+// Nodes each thread owns (rows by / nodes-per-thread apart), or -2: work groups of
+// two threads per node, half of them owning none (the XT = 2 kernels).
+extern const int kD2Q9NodesPerThread[];
+const int kD2Q9NodesPerThread[] = {1, 1, 1, 1, 1, 1, 2, 2, -2, -2, -2, -2};
 
 hipError_t d2q9_launch_step(const StepArgs& a, int grid, hipStream_t s, int precision, int variant, int shape,
                             int fields) {

@@ -452,19 +452,21 @@ def test_fp32_deviation_storage_tracks_fp64(lattice, scheme):
     sim.close()
 
 
-@pytest.mark.parametrize("stores", ["device", "streaming"])
-def test_full_size_512sq_cs_droplet_one_step(stores):
+@pytest.mark.parametrize("shape,dims,stores", [(9, (32, 8, -2), "device"), (8, (32, 16, -2), "device"),
+                                               (0, (32, 16, 1), "device"), (0, (32, 16, 1), "streaming")])
+def test_full_size_512sq_cs_droplet_one_step(shape, dims, stores):
     """The 512 x 512 Carnahan-Starling droplet (r = 80, T/Tc = 0.8, kappa = 0.01,
-    tau = 0.8) in the launch configuration the benchmark times (32 x 16 tiles,
-    device-scope stores, the tuner's pick) and with streaming stores: whole-lattice
-    parity after one step and after two graph-replayed steps."""
+    tau = 0.8) in the launch configurations the benchmark's tuner picks between (32 x 8
+    and 32 x 16 tiles with two threads per node, device-scope stores) and with one
+    thread per node, device-scope and streaming stores: whole-lattice parity after one
+    step and after two graph-replayed steps."""
     p = runtime.params("D2Q9", 512, 512, 1, eos="CS", T_over_Tc=0.8, kappa=0.01, tau=0.8)
     rho0 = _droplet((512, 512), "CS", 0.8, 80.0)
     sim = runtime.LBM(p)
-    sim.set_tile_shape(0)
-    assert sim.tile_shape() == (32, 16, 1)
+    sim.set_tile_shape(shape)
+    assert sim.tile_shape() == dims
     sim.set_store_mode(stores)
-    print(f"case 512^2 full size, {stores} stores", flush=True)
+    print(f"case 512^2 full size, tile {dims}, {stores} stores", flush=True)
     sim.init(rho0)
     refs = oracle_run(p, rho0, [1, 3])
     sim.step(1)
