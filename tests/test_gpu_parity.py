@@ -354,8 +354,9 @@ def test_chemical_potential_across_the_density_range(eos):
     of the EOS over six decades of its argument.  f, rho and mu are held to 1e-12;
     u to 1e-11: near the packing limit mu grows like 1/(1 - b rho), and the force is
     a difference of large, nearly equal mu values, so last-bit differences in mu
-    (the kernels' logarithm is within 2 ulp of the exact one, the oracle's within
-    half an ulp) grow there (measured 1.5e-12 for vdW, 1.5e-13 for CS)."""
+    (the kernels' logarithm and reciprocal are within a few ulp of the exact ones,
+    the oracle's within half an ulp) grow there (measured 1.5e-12 for vdW, 1.5e-13
+    for CS, with a correctly rounded reciprocal)."""
     nx, ny = 256, 16
     p = runtime.params("D2Q9", nx, ny, 1, eos=eos, T_over_Tc=0.8, kappa=0.01, tau=0.8)
     rho_max = (1.0 if eos == "vdW" else 4.0) / p.b
