@@ -167,7 +167,9 @@ typedef struct lbm_ctx lbm_ctx;
  * Eq. 1 and the relaxation rates of Eq. 8); T_c = 8a/(27Rb) for vdW (Sec. IV A).
  * Errors: LBM_ERR_ARG for an invalid parameter (the message names it),
  * LBM_ERR_UNSUPPORTED for a valid combination the library does not implement
- * (e.g. MRT or plates on D3Q19, or more than 2^31 populations in one lattice). */
+ * (e.g. MRT or plates on D3Q19, or a population array beyond 4 GB: more than
+ * 2^30 nodes in one float32 lattice, 2^29 in float64; the kernels address each
+ * array with unsigned 32-bit byte offsets). */
 int lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
 
 /* Create a handle for `count` independent lattices advanced together by one

@@ -236,8 +236,10 @@ int check_params(const lbm_params& p) {
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(LBM_ERR_ARG, "lattice extents must be >= 1");
     if (p.lattice == LBM_D2Q9 && p.nz != 1) return fail(LBM_ERR_ARG, "D2Q9 requires nz == 1");
     const long long n = (long long)p.nx * p.ny * p.nz;
-    if (n * (p.lattice == LBM_D2Q9 ? 9 : 19) >= (1LL << 31))
-        return fail(LBM_ERR_UNSUPPORTED, "one lattice may hold at most 2^31 populations");
+    // the kernels address one population array with unsigned 32-bit byte offsets
+    if (n * (p.precision == LBM_FP32_DEV ? 4 : 8) > (1LL << 32))
+        return fail(LBM_ERR_UNSUPPORTED,
+                    "one population array of a lattice may span at most 4 GB (2^30 nodes in float32, 2^29 in float64)");
     if (p.eos != LBM_EOS_VDW && p.eos != LBM_EOS_CS) return fail(LBM_ERR_ARG, "eos must be VDW or CS");
     if (!(p.a >= 0) || !(p.b > 0) || !(p.R > 0)) return fail(LBM_ERR_ARG, "EOS constants need a >= 0, b > 0, R > 0");
     if (!(p.T_over_Tc > 0)) return fail(LBM_ERR_ARG, "T_over_Tc must be > 0");
@@ -460,6 +462,10 @@ int graph_for(lbm_ctx* h, int n, hipGraphExec_t* out) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     h->graphs[key] = ex;
+    // the executable graph goes to the device now, so that its first replay does
+    // not pay for the upload
+    e = hipGraphUpload(ex, h->stream);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("hipGraphUpload: ") + hipGetErrorString(e));
     *out = ex;
     return LBM_OK;
 }

@@ -546,11 +546,8 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + lat, acc.status);
     } else {
-        block_reduce_store<TPB>(acc, args.partial + t_idx, s_red, s_ured);
-        if (threadIdx.x == 0) {
-            const unsigned st = args.partial[t_idx].status;
-            if (st) atomicOr(args.status + lat, st);
-        }
+        const unsigned st = block_reduce_store<TPB>(acc, args.partial + t_idx, s_red, s_ured);
+        if (threadIdx.x == 0 && st != 0u) atomicOr(args.status + lat, st);
     }
 }
 

@@ -33,13 +33,14 @@ __device__ constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 
 // Pull the 19 populations arriving at a node (Eq. 10: population a comes from
 // x - e_a).  xy[k] is the byte offset of the in-plane neighbour (dx, dy) =
 // (k % 3 - 1, k / 3 - 1) within a plane, fixed over a sweep; zb[k] the byte offset
-// of plane z - 1 + k (wave-uniform), so each load costs one vector add.
+// of plane z - 1 + k (wave-uniform), so each load costs one vector add.  Offsets are
+// unsigned 32-bit: one population array may span up to 4 GB.
 template <typename S, typename T>
-__device__ __forceinline__ void pull(const S* const (&p)[19], const int (&xy)[9], const int (&zb)[3], T f[19]) {
+__device__ __forceinline__ void pull(const S* const (&p)[19], const int (&xy)[9], const unsigned (&zb)[3], T f[19]) {
 #pragma unroll
     for (int a = 0; a < 19; ++a)
         f[a] = (T)*reinterpret_cast<const S*>(reinterpret_cast<const char*>(p[a]) +
-                                             (unsigned)(xy[(1 - EY[a]) * 3 + (1 - EX[a])] + zb[1 - EZ[a]]));
+                                             ((unsigned)xy[(1 - EY[a]) * 3 + (1 - EX[a])] + zb[1 - EZ[a]]));
 }
 
 // Sum of the moving populations, then the density deviation with the rest
@@ -254,9 +255,10 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) oxy[k] = (Y[k / 3] + X[k % 3]) * WS;
     }
-    auto zbytes = [&](int z, int (&zb)[3]) {
+    const unsigned plane_bytes = (unsigned)NXY * (unsigned)WS;
+    auto zbytes = [&](int z, unsigned (&zb)[3]) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) zb[k] = wrap(z - 1 + k, nz, sz) * NXY * WS;
+        for (int k = 0; k < 3; ++k) zb[k] = (unsigned)wrap(z - 1 + k, nz, sz) * plane_bytes;
     };
 
     T fifo[FIFO ? 4 : 1][19];
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         if (it < NIT) {
             T f[19];
             T fh[HP][19];
-            int zb[3];
+            unsigned zb[3];
             zbytes(za, zb);
             pull<S, T>(pp, oxy, zb, f);
 #pragma unroll
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
 #pragma unroll
                 for (int a = 0; a < 19; ++a) f[a] = fifo[KR][a];
             } else {
-                int zb[3];
+                unsigned zb[3];
                 zbytes(zd, zb);
                 pull<S, T>(pp, oxy, zb, f);
             }
@@ -530,11 +532,8 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + tile.lat, acc.status);
     } else {
-        block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
-        if (threadIdx.x == 0) {
-            const unsigned st = args.partial[t_idx].status;
-            if (st != 0u) atomicOr(args.status + tile.lat, st);
-        }
+        const unsigned st = block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
+        if (threadIdx.x == 0 && st != 0u) atomicOr(args.status + tile.lat, st);
     }
 }
 
@@ -585,7 +584,7 @@ __global__ void init_kernel(S* state, const LatticeRec* recs, int nlat, const do
     for (int a = 0; a < 19; ++a) {
         const int sx = ((x - EX[a]) % nx + nx) % nx, sy = ((y - EY[a]) % ny + ny) % ny,
                   sz = ((z - EZ[a]) % nz + nz) % nz;
-        st[a * N + (sz * ny + sy) * nx + sx] = (S)feq[a];
+        st[(size_t)a * N + (sz * ny + sy) * nx + sx] = (S)feq[a];
     }
 }
 

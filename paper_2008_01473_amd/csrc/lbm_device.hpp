@@ -248,9 +248,11 @@ struct DiagAcc {
     unsigned status = 0;
 };
 
+// Returns the tile's status bits in thread 0 (the value it stored), so that the
+// caller need not read the record back from memory.
 template <int NT>
-__device__ __forceinline__ void block_reduce_store(const DiagAcc& a, DiagPartial* out, double* scratch,
-                                                   unsigned* uscratch) {
+__device__ __forceinline__ unsigned block_reduce_store(const DiagAcc& a, DiagPartial* out, double* scratch,
+                                                       unsigned* uscratch) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
@@ -276,7 +278,9 @@ __device__ __forceinline__ void block_reduce_store(const DiagAcc& a, DiagPartial
             p.status |= uscratch[i];
         }
         *out = p;
+        return p.status;
     }
+    return 0u;
 }
 
 // BGK update of a pair of opposite velocities e and -e (same weight w):

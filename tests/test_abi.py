@@ -223,3 +223,17 @@ def test_fixed_z_chunk_on_the_host():
     assert L.lbm_set_zchunk(h, 32) == lib_mod.LBM_ERR_UNSUPPORTED
     L.lbm_destroy(h)
     assert L.lbm_get_zchunk(None) == -1
+
+
+def test_lattice_size_limit_is_four_gigabytes_per_population_array():
+    """One population array may span up to 4 GB (unsigned 32-bit byte offsets): a
+    float32 D3Q19 lattice of 2^30 nodes is accepted, one more plane is refused;
+    float64 allows half the nodes.  Only the plan is made (no device memory)."""
+    L = lib()
+    for prec, nz_ok in (("fp32", 1024), ("fp64", 512)):
+        rc, h = _create(runtime.params(lattice="D3Q19", nx=1024, ny=1024, nz=nz_ok, precision=prec))
+        assert rc == lib_mod.LBM_OK, prec
+        L.lbm_destroy(h)
+        rc, h = _create(runtime.params(lattice="D3Q19", nx=1024, ny=1024, nz=nz_ok + 1, precision=prec))
+        assert rc == lib_mod.LBM_ERR_UNSUPPORTED, prec
+

@@ -568,6 +568,55 @@ def test_full_size_256cube_d3q19_z_slab_windows():
     sim.close()
 
 
+def test_d3q19_population_arrays_beyond_2GiB():
+    """A float32 D3Q19 lattice whose population arrays span more than 2^31 bytes
+    (128 x 128 x 33000 nodes: 2.16 GB per array, 82 GB of state), in the benchmark's
+    launch configuration (64 x 4 columns, 128-slice chunks): the kernels' unsigned
+    32-bit byte offsets reach past 2^31 in the upper slices.  After two steps, the
+    fields (rho, u, mu) of 8-slice windows high in the lattice (through a droplet
+    there, offsets above 2^31) and low in it against the oracle run on the window plus
+    12 slices on either side (the fields after two steps depend on the state within
+    11 nodes), vdW T/Tc = 0.85, r = 20."""
+    nx = ny = 128
+    nz = 33000
+    N = nx * ny * nz
+    assert N * 4 > 2**31
+    m = _maxwell("vdW", 0.85)
+    p = runtime.params("D3Q19", nx, ny, nz, eos="vdW", T_over_Tc=0.85, kappa=0.02, tau=1.0, precision="fp32")
+    zc_hi = 32900
+    box = 40
+    rho0 = np.full((nz, ny, nx), m["rho_g"])
+    # the droplet's neighbourhood, built on a local box and placed at zc_hi
+    loc = inputs.droplet((2 * box, ny, nx), m["rho_g"], m["rho_l"], 20.0, 5.0, noise=1e-4, seed=5)
+    rho0[zc_hi - box:zc_hi + box] = loc
+    print(f"case D3Q19 fp32 {nx}x{ny}x{nz}: {N * 4 / 2**30:.2f} GiB per population array", flush=True)
+    sim = runtime.LBM(p)
+    _bench_d3q19_config(sim)
+    sim.init(rho0.reshape(-1))
+    sim.step(2)
+    rho, u, mu = sim.moments()
+    rho, u, mu = rho.view(nz, ny, nx), u.view(3, nz, ny, nx), mu.view(nz, ny, nx)
+    prm = oracle_params(p)
+    margin = 12
+    for z0 in (zc_hi - 4, zc_hi + 12, 200):
+        zs = np.arange(z0 - margin, z0 + 8 + margin) % nz
+        assert z0 < 1000 or z0 * nx * ny * 4 > 2**31
+        fr = model.run(model.init(torch.as_tensor(rho0[zs]), prm), prm, 2)
+        fl = model.fields(fr, prm)
+        win = torch.as_tensor(zs[margin:margin + 8]).cuda()
+        inner = slice(margin, margin + 8)
+        rs = float(fl["rho"][inner].abs().max())
+        er = float((rho.index_select(0, win).cpu() - fl["rho"][inner]).abs().max()) / max(rs, m["rho_l"])
+        eu = float((u.index_select(1, win).cpu() - fl["u"][:, inner]).abs().max())
+        em = float((mu.index_select(0, win).cpu() - fl["mu"][inner]).abs().max())
+        print(f"  window z={z0}..{z0 + 7}: rho {er:.2e} u_abs {eu:.2e} mu_abs {em:.2e} "
+              f"(liquid in window: {rs > 2 * m['rho_g']})", flush=True)
+        assert er < 2e-6 and eu < 2e-6 and em < 2e-6
+    d = sim.diagnostics()[0]
+    assert d["status"] == 0
+    sim.close()
+
+
 def test_standard_scheme_droplet_instability_is_flagged():
     """Sec. IV B: the standard scheme is unstable for the droplet at T/Tc = 0.7 (its
     blow-up is detected and flagged), while the improved scheme at T/Tc = 0.75 stays
