@@ -60,7 +60,8 @@ int main() {
     CHECK(lbm_node_offset(h, 1) == -1);
     for (int s = 0; s < lbm_num_tile_shapes(h); ++s) {
         int bx = 0, by = 0, bz = 0;
-        CHECK(lbm_describe_tile_shape(h, s, &bx, &by, &bz) == LBM_OK && bx > 0 && by > 0 && bz > 0);
+        // D2Q9: bz > 0 nodes per thread, or -2 for two threads per node
+        CHECK(lbm_describe_tile_shape(h, s, &bx, &by, &bz) == LBM_OK && bx > 0 && by > 0 && (bz > 0 || bz == -2));
         const int rc = lbm_set_tile_shape(h, s);       // unbound: plans only
         CHECK(rc == LBM_OK || rc == LBM_ERR_UNSUPPORTED);
     }
@@ -98,7 +99,8 @@ int main() {
         {"mrt rates", [](lbm_params& q) { q.collision = LBM_MRT; q.tau_e = 0.4; q.tau_s = 1; q.tau_q = 1; }, LBM_ERR_ARG},
         {"c0", [](lbm_params& q) { q.c0 = -1; }, LBM_ERR_ARG},
         {"walls", [](lbm_params& q) { q.walls = 2; }, LBM_ERR_ARG},
-        {"too many populations", [](lbm_params& q) { q.nx = 1 << 15; q.ny = 1 << 14; }, LBM_ERR_UNSUPPORTED},
+        {"population array beyond 4 GB", [](lbm_params& q) { q.nx = 1 << 15; q.ny = (1 << 14) + 1; },
+         LBM_ERR_UNSUPPORTED},
     };
     for (const Bad& b : bad) {
         lbm_params q = base(LBM_D2Q9, 32, 24, 1);
