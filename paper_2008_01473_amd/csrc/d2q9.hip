@@ -456,6 +456,13 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
 
     // ---- stage D: collide and store (or write fields) ----
     DiagAcc acc;
+    // With two threads per node and float64 storage the helper threads, idle in
+    // stage D, take the diagnostics after it from LDS (the density there is the
+    // owner's population sum in stage D's order), so that the owners collide with
+    // the registers of the plain step; float32 storage sums the exact node mass
+    // from the owner's populations.
+    constexpr bool HDIAG = MODE == kStepDiag && XT == 2 && !F32;
+    static_assert(!HDIAG || (NPT == 1 && NT % 64 == 0), "helper diagnostics: one node per owner, whole waves");
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
     T (&fo)[9] = fown[p];
@@ -534,20 +541,38 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
                 for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
             }
         }
-        acc.mass += F32 ? m_in : (double)drho;
-        acc.mx += (double)(r * ux);
-        acc.my += (double)(r * uy);
-        acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
-        acc.mumin = fmin(acc.mumin, mu);
-        acc.mumax = fmax(acc.mumax, mu);
-        acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
+        if constexpr (!HDIAG) {
+            acc.mass += F32 ? m_in : (double)drho;
+            acc.mx += (double)(r * ux);
+            acc.my += (double)(r * uy);
+            acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
+            acc.mumin = fmin(acc.mumin, mu);
+            acc.mumax = fmax(acc.mumax, mu);
+            acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
+        }
     }
+    }
+    if constexpr (HDIAG) {
+        const int ht = tid - NT, hx = ht % BX, hy = ht / BX;
+        if (!owner && x0 + hx < nx && y0 + hy < ny) {
+            const T x = s_rho[(hy + 3) * W3 + hx + 3];
+            const T r = rho_ref + x;
+            const double mu = muref.mu_off + (double)s_mu[(hy + 2) * W2 + hx + 2];
+            const T ux = s_u[ht], uy = s_u[NN + ht];
+            acc.mass += (double)x;
+            acc.mx += (double)(r * ux);
+            acc.my += (double)(r * uy);
+            acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
+            acc.mumin = fmin(acc.mumin, mu);
+            acc.mumax = fmax(acc.mumax, mu);
+            acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
+        }
     }
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + lat, acc.status);
     } else {
-        const unsigned st = block_reduce_store<TPB>(acc, args.partial + t_idx, s_red, s_ured);
-        if (threadIdx.x == 0 && st != 0u) atomicOr(args.status + lat, st);
+        const unsigned st = block_reduce_store<TPB, HDIAG ? NT / 64 : 0>(acc, args.partial + t_idx, s_red, s_ured);
+        if (st != 0u) atomicOr(args.status + lat, st);
     }
 }
 

@@ -533,7 +533,7 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
         if (acc.status) atomicOr(args.status + tile.lat, acc.status);
     } else {
         const unsigned st = block_reduce_store<NT>(acc, args.partial + t_idx, s_red, s_ured);
-        if (threadIdx.x == 0 && st != 0u) atomicOr(args.status + tile.lat, st);
+        if (st != 0u) atomicOr(args.status + tile.lat, st);
     }
 }
 

@@ -248,26 +248,30 @@ struct DiagAcc {
     unsigned status = 0;
 };
 
-// Returns the tile's status bits in thread 0 (the value it stored), so that the
-// caller need not read the record back from memory.
-template <int NT>
+// Waves W0 .. NT/64 - 1 hold the tile's contributions (the others only pass the
+// barrier).  Returns the tile's status bits in thread 64 W0 (the value it stored),
+// so that the caller need not read the record back from memory; 0 elsewhere.
+template <int NT, int W0 = 0>
 __device__ __forceinline__ unsigned block_reduce_store(const DiagAcc& a, DiagPartial* out, double* scratch,
                                                        unsigned* uscratch) {
     constexpr int NW = NT / 64;
+    static_assert(W0 >= 0 && W0 < NW, "no wave holds the contributions");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
-                   wave_max(a.umax2), wave_min(a.mumin), wave_max(a.mumax)};
-    unsigned st = wave_or(a.status);
-    if (lane == 0) {
-        for (int k = 0; k < 7; ++k) scratch[k * NW + w] = v[k];
-        uscratch[w] = st;
+    if (w >= W0) {
+        double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
+                       wave_max(a.umax2), wave_min(a.mumin), wave_max(a.mumax)};
+        unsigned st = wave_or(a.status);
+        if (lane == 0) {
+            for (int k = 0; k < 7; ++k) scratch[k * NW + w] = v[k];
+            uscratch[w] = st;
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 64 * W0) {
         DiagPartial p;
         p.mass = 0; p.momx = 0; p.momy = 0; p.momz = 0;
         p.umax2 = 0; p.mumin = 1e300; p.mumax = -1e300; p.status = 0; p.pad = 0;
-        for (int i = 0; i < NW; ++i) {
+        for (int i = W0; i < NW; ++i) {
             p.mass += scratch[0 * NW + i];
             p.momx += scratch[1 * NW + i];
             p.momy += scratch[2 * NW + i];

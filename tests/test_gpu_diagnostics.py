@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_2008_01473_amd import runtime  # noqa: E402
+from paper_2008_01473_amd import _lib, runtime  # noqa: E402
 from oracle import eos as oeos  # noqa: E402
 
 
@@ -67,14 +67,28 @@ def _check(got, ref, tol, label):
         assert abs(got[key] - ref[key]) <= tol * max(abs(ref[key]), 1e-3)
 
 
-def _run_and_check(plist, radii, n, tol, prec_label):
+_REFS = {}
+
+
+def _run_and_check(plist, radii, n, tol, prec_label, tile=None):
     sim = runtime.LBM(plist)
+    if tile is not None:
+        try:
+            sim.set_tile_shape(tile)
+        except _lib.LBMError as e:
+            sim.close()
+            if e.code == _lib.LBM_ERR_UNSUPPORTED:
+                pytest.skip(f"tile shape {tile} refused for this lattice: {e}")
+            raise
     rho_all, u_all, refs = [], [], []
     for i, p in enumerate(plist):
         rho0, u0 = _inputs(p, radii[i], seed=i)
         rho_all.append(rho0.reshape(-1))
         u_all.append(u0.reshape(len(u0), -1))
-        refs.append(_oracle_diag(p, rho0, u0, [n - 1, n]))
+        key = (prec_label, i, n)
+        if key not in _REFS:
+            _REFS[key] = _oracle_diag(p, rho0, u0, [n - 1, n])
+        refs.append(_REFS[key])
     D = sim.D
     u_cat = np.concatenate([np.concatenate([u[k] for u in u_all]) for k in range(D)])
     sim.init(np.concatenate(rho_all), u_cat)
@@ -97,6 +111,39 @@ def test_d2q9_single_lattice_diagnostics(scheme, form):
     p = runtime.params("D2Q9", 70, 37, 1, eos="CS", T_over_Tc=0.85, kappa=0.02, tau=0.8, scheme=scheme,
                        force_form=form)
     _run_and_check([p], [9.0], 6, 1e-12, f"D2Q9 {scheme}/{form}")
+
+
+_D2Q9_SHAPES = 12
+
+
+def test_d2q9_tile_shape_count():
+    p = runtime.params("D2Q9", 16, 16, 1)
+    sim = runtime.LBM([p])
+    assert sim.num_tile_shapes() == _D2Q9_SHAPES
+    sim.close()
+
+
+@pytest.mark.parametrize("tile", range(_D2Q9_SHAPES))
+@pytest.mark.parametrize("scheme,form", [("improved", "chempot"), ("standard", "chempot"), ("standard", "ptensor")])
+def test_d2q9_diagnostics_every_tile_shape(scheme, form, tile):
+    """Every tile shape reduces the diagnostics of its own tiling: one node per
+    thread, two nodes per thread, and two threads per node (where the helper
+    threads take the float64 diagnostics from LDS)."""
+    p = runtime.params("D2Q9", 70, 37, 1, eos="CS", T_over_Tc=0.85, kappa=0.02, tau=0.8, scheme=scheme,
+                       force_form=form)
+    _run_and_check([p], [9.0], 6, 1e-12, f"D2Q9 {scheme}/{form}", tile=tile)
+
+
+@pytest.mark.parametrize("tile", range(_D2Q9_SHAPES))
+def test_d2q9_batch_with_mrt_and_plates_diagnostics_every_tile_shape(tile):
+    """A launch whose lattices use the MRT collision and plates carries both
+    features' code: the diagnostics of each lattice through every tile shape."""
+    plist = [runtime.params("D2Q9", 48, 40, 1, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=1.0),
+             runtime.params("D2Q9", 64, 64, 1, eos="vdW", T_over_Tc=0.75, kappa=0.018, tau=1.0, collision="mrt",
+                            tau_e=0.9, tau_s=1.1, tau_q=1.2),
+             runtime.params("D2Q9", 45, 37, 1, eos="vdW", T_over_Tc=0.8, kappa=0.02, tau=0.8,
+                            walls=(-0.03, 0.03))]
+    _run_and_check(plist, [8.0, 12.0, 7.0], 5, 1e-12, "D2Q9 batch mrt+plates", tile=tile)
 
 
 @pytest.mark.parametrize("scheme", ["improved", "standard"])
