@@ -199,7 +199,9 @@ int lbm_init(lbm_ctx* h, const double* rho0, const double* u0);
 
 /* Advance n >= 0 steps (Eqs. 7-10 with the scheme's force and sources), one
  * fused kernel per step; n >= 2 steps are replayed from a captured HIP graph.
- * Lattices whose blow-up flags are set are skipped from then on. */
+ * Every step checks its input for blow-up; lattices whose blow-up flags are
+ * set are skipped from then on.  The steps reduce no diagnostics: see
+ * lbm_diagnostics. */
 int lbm_step(lbm_ctx* h, int n);
 
 /* Capture, without running them, the HIP graphs that lbm_step(h, n) will replay
@@ -213,8 +215,11 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu);
 
 /* Copy the diagnostics of every lattice (count entries) to host memory.  They
  * refer to the time level of the most recent lbm_step input or lbm_moments
- * call (lbm_diag.step).  Blocks until the stream has finished.  Returns
+ * call (lbm_diag.step).  After lbm_step they are reduced here, by one read-out
+ * launch over the last step's input, which the second population buffer holds
+ * until the next step.  Blocks until the stream has finished.  Returns
  * LBM_ERR_BLOWUP if any lattice has its status set (out is still filled).
+ * The sums describe the state as it is, NaNs of a blown-up state included.
  * Lattices it reports blown up leave the launch plan (their populations stay
  * frozen and no work group is spent on them; captured graphs are re-captured
  * on the next lbm_step) until lbm_init, lbm_set_f or lbm_set_state clears the

@@ -109,6 +109,9 @@ struct lbm_ctx {
     std::vector<long long> frozen_step;
     std::vector<DiagOut> diag_cache;
     bool diag_cache_valid = false;
+    // lbm_step leaves the reduction of its last input's diagnostics to
+    // lbm_diagnostics, which reads that time level from the other buffer
+    bool diag_pending = false;
 
     // A tuning index names a kernel tile shape and, for D3Q19, also how many
     // work groups the z-chunking aims at (kZTargets): index = shape * 3 + target.
@@ -631,6 +634,7 @@ int lbm_init(lbm_ctx* h, const double* rho0, const double* u0) {
     if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->t = 0;
     h->t_diag = -1;
+    h->diag_pending = false;
     h->inited = true;
     return LBM_OK;
 }
@@ -641,26 +645,26 @@ int lbm_step(lbm_ctx* h, int n) {
     if (!h->inited) return fail(LBM_ERR_STATE, "lbm_init or lbm_set_f first");
     if (n == 0) return LBM_OK;
     const long long t0 = h->t;
-    // all but the last step: graph replays of even length (the current buffer
-    // is unchanged by an even number of steps), then single launches
-    int body = n - 1;
+    // graph replays of even length (the current buffer is unchanged by an even
+    // number of steps), then single launches
+    int left = n;
     if (h->use_graphs) {
-        while (body >= 2) {
-            const int len = body >= kGraphChunk ? kGraphChunk : (body & ~1);
+        while (left >= 2) {
+            const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
             hipGraphExec_t ex;
             int rc = graph_for(h, len, &ex);
             if (rc != LBM_OK) return rc;
             HIP_TRY(hipGraphLaunch(ex, h->stream));
-            body -= len;
+            left -= len;
         }
     }
-    int rc = enqueue_steps(h, body, h->stream, kStep);
-    if (rc != LBM_OK) return rc;
-    // the last step also reduces the diagnostics of its input time level
-    rc = enqueue_steps(h, 1, h->stream, kStepDiag);
+    int rc = enqueue_steps(h, left, h->stream, kStep);
     if (rc != LBM_OK) return rc;
     h->t = t0 + n;
+    // The diagnostics refer to the last step's input, which the other buffer
+    // holds until the next step; lbm_diagnostics reduces them when asked.
     h->t_diag = h->t - 1;
+    h->diag_pending = true;
     h->diag_cache_valid = false;
     return LBM_OK;
 }
@@ -670,7 +674,7 @@ int lbm_prepare_steps(lbm_ctx* h, int n) {
     if (n < 0) return fail(LBM_ERR_ARG, "n must be >= 0");
     if (!h->bound) return fail(LBM_ERR_STATE, "lbm_bind first");
     if (!h->use_graphs) return LBM_OK;
-    int left = n - 1;
+    int left = n;
     while (left >= 2) {
         const int len = left >= kGraphChunk ? kGraphChunk : (left & ~1);
         hipGraphExec_t ex;
@@ -692,6 +696,7 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu) {
     a.mu_out = mu;
     HIP_TRY(launch_step(h, a, kFields, h->stream));
     h->t_diag = h->t;
+    h->diag_pending = false;
     h->diag_cache_valid = false;
     return LBM_OK;
 }
@@ -704,6 +709,13 @@ int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
     if (h->diag_cache_valid) {
         tmp = h->diag_cache;
     } else {
+        if (h->diag_pending) {
+            // the read-out of the last step's input (the other buffer): per-tile partials only
+            StepArgs a = base_args(h);
+            a.src = h->buf[h->cur ^ 1];
+            HIP_TRY(launch_step(h, a, kFields, h->stream));
+            h->diag_pending = false;
+        }
         HIP_TRY(launch_finalize(h->d_partial(), h->d_recs(), h->d_status(), h->d_diag(), n, h->stream));
         HIP_TRY(hipMemcpyAsync(tmp.data(), h->d_diag(), n * sizeof(DiagOut), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -775,6 +787,7 @@ int lbm_set_f(lbm_ctx* h, const double* f) {
     if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->inited = true;
     h->t_diag = -1;
+    h->diag_pending = false;
     return LBM_OK;
 }
 
@@ -793,6 +806,7 @@ int lbm_set_state(lbm_ctx* h, const void* src, long long step) {
     if (int rc0 = reset_status(h); rc0 != LBM_OK) return rc0;
     h->t = step;
     h->t_diag = -1;
+    h->diag_pending = false;
     h->inited = true;
     return LBM_OK;
 }
@@ -944,6 +958,7 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->t_diag = -1;
+    h->diag_pending = false;
     h->diag_cache_valid = false;
     return best;
 }
@@ -1134,6 +1149,7 @@ int lbm_adjoint_segment(lbm_ctx* h, const void* checkpoint, long long t0, int m,
     }
     h->t = t0 + m;
     h->t_diag = -1;
+    h->diag_pending = false;
     h->inited = true;
     return LBM_OK;
 }
@@ -1214,6 +1230,7 @@ int lbm_adjoint_sweep(lbm_ctx* h, const void* const* checkpoints, const long lon
     }
     h->diag_cache_valid = false;
     h->t_diag = -1;
+    h->diag_pending = false;
     return LBM_OK;
 }
 

@@ -223,8 +223,8 @@ __device__ __forceinline__ void equilibrium(T feq[9], T rho, T drho, T ux, T uy,
 //   B  mu = mu_EOS(rho) - kappa lap(rho) on tile + 2 (Eq. 2); P on tile + 2 (P-tensor form)
 //   C  F (Eq. 13 / Eq. 24), u = (j + F/2)/rho (Eq. 12), psi = phi u (Eq. 29) on tile + 1
 //   D  collision (Eq. 9 / Eq. 28 with Lambda = I/tau) and store, or field output
-// MODE (lbm::Mode) selects collide-and-store, the same plus per-tile
-// diagnostics, or writing rho, u, mu of the current time level.
+// MODE (lbm::Mode) selects collide-and-store, or the read-out of rho, u, mu and
+// the per-tile diagnostics of the input time level (no store).
 // FEAT bit 1: lattices of the launch may use the MRT collision; bit 2: they may
 // have plates (the lattice record decides); launches without them carry no such code.
 // XT: work-group threads per own thread.  With XT = 2 the second half of the work
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
     __shared__ T s_F[2 * NN], s_u[2 * NN];
     __shared__ T s_P[PT ? 3 * H2 * W2 : 1];
     __shared__ double s_red[7 * (TPB / 64)];
-    __shared__ unsigned s_ured[TPB / 64];
+    __shared__ unsigned s_ured[TPB / 64 + 1];     // per-wave status bits, then the arrival count
 
     const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
     if (t_idx >= args.ntiles) return;
@@ -366,12 +366,16 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
             }
         }
     }
-    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
-    // this one runs, so one thread reads it and the whole block follows.  (The
-    // runtime leaves the tiles of lattices it has reported blown up out of its
-    // plan, so this mostly catches lattices that blew up since.)
+    // Blown-up lattices are frozen: steps skip them.  The flag can be raised by
+    // other blocks while this one runs, so one thread reads it and the whole block
+    // follows.  (The runtime leaves the tiles of lattices it has reported blown up
+    // out of its plan, so this mostly catches lattices that blew up since.)  A
+    // read-out, which stores no populations, covers every tile.
     __shared__ unsigned s_skip;
-    if (tid == 0) s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
+    if (tid == 0) {
+        s_skip = __atomic_load_n(args.status + lat, __ATOMIC_RELAXED);
+        s_ured[TPB / 64] = 0u;
+    }
     // a mirror image beyond a plate carries the reflected momentum (j_y negated)
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
         }
     }
     __syncthreads();
-    if (s_skip != 0u) return;
+    if (MODE == kStep && s_skip != 0u) return;
 
     // ---- stage B: chemical potential (and pressure tensor) on tile + 2 ----
     for (int k = tid; k < H2 * W2; k += TPB) {
@@ -456,13 +460,6 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
 
     // ---- stage D: collide and store (or write fields) ----
     DiagAcc acc;
-    // With two threads per node and float64 storage the helper threads, idle in
-    // stage D, take the diagnostics after it from LDS (the density there is the
-    // owner's population sum in stage D's order), so that the owners collide with
-    // the registers of the plain step; float32 storage sums the exact node mass
-    // from the owner's populations.
-    constexpr bool HDIAG = MODE == kStepDiag && XT == 2 && !F32;
-    static_assert(!HDIAG || (NPT == 1 && NT % 64 == 0), "helper diagnostics: one node per owner, whole waves");
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
     T (&fo)[9] = fown[p];
@@ -541,37 +538,19 @@ __global__ __launch_bounds__(BX* BY* XT) void step_kernel(StepArgs args) {
                 for (int a = 0; a < 9; ++a) st_off(dst + (size_t)a * N, (unsigned)node, (S)fo[a]);
             }
         }
-        if constexpr (!HDIAG) {
-            acc.mass += F32 ? m_in : (double)drho;
-            acc.mx += (double)(r * ux);
-            acc.my += (double)(r * uy);
-            acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
-            acc.mumin = fmin(acc.mumin, mu);
-            acc.mumax = fmax(acc.mumax, mu);
-            acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
-        }
+        acc.mass += F32 ? m_in : (double)drho;
+        acc.mx += (double)(r * ux);
+        acc.my += (double)(r * uy);
+        acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
+        acc.mumin = fmin(acc.mumin, mu);
+        acc.mumax = fmax(acc.mumax, mu);
+        acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
     }
-    }
-    if constexpr (HDIAG) {
-        const int ht = tid - NT, hx = ht % BX, hy = ht / BX;
-        if (!owner && x0 + hx < nx && y0 + hy < ny) {
-            const T x = s_rho[(hy + 3) * W3 + hx + 3];
-            const T r = rho_ref + x;
-            const double mu = muref.mu_off + (double)s_mu[(hy + 2) * W2 + hx + 2];
-            const T ux = s_u[ht], uy = s_u[NN + ht];
-            acc.mass += (double)x;
-            acc.mx += (double)(r * ux);
-            acc.my += (double)(r * uy);
-            acc.umax2 = fmax(acc.umax2, (double)(ux * ux + uy * uy));
-            acc.mumin = fmin(acc.mumin, mu);
-            acc.mumax = fmax(acc.mumax, mu);
-            acc.status |= blowup_bits<T>(r, ux, uy, T(0), rho_max);
-        }
     }
     if constexpr (MODE == kStep) {
         if (acc.status) atomicOr(args.status + lat, acc.status);
     } else {
-        const unsigned st = block_reduce_store<TPB, HDIAG ? NT / 64 : 0>(acc, args.partial + t_idx, s_red, s_ured);
+        const unsigned st = block_reduce_store<TPB>(acc, args.partial + t_idx, s_red, s_ured);
         if (st != 0u) atomicOr(args.status + lat, st);
     }
 }
@@ -693,8 +672,6 @@ hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
             }
         }
         hipLaunchKernelGGL((d2q9::step_kernel<S, T, V, BX, BY, kFields, 0, NPT, XT>), g, b, 0, s, a);
-    } else if (mode == kStepDiag) {
-        launch_feat<S, T, V, BX, BY, kStepDiag, NPT, XT>(a, feat, g, b, s);
     } else {
         launch_feat<S, T, V, BX, BY, kStep, NPT, XT>(a, feat, g, b, s);
     }

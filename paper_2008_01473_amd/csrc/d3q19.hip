@@ -201,18 +201,22 @@ __global__ __launch_bounds__(BX* BY) void step_kernel(StepArgs args) {
     __shared__ T s_P[PT ? 4 * 3 * A2 : 1];      // p, d_x rho, d_y rho, d_z rho; ring of 3 slices
     __shared__ T s_fu[6 * 2 * NT];              // Fx Fy Fz ux uy uz of the tile, 2 slices
     __shared__ double s_red[7 * (NT / 64)];
-    __shared__ unsigned s_ured[NT / 64];
+    __shared__ unsigned s_ured[NT / 64 + 1];      // per-wave status bits, then the arrival count
 
     const int t_idx = tile_of_block(blockIdx.x, args.tiles_per_xcd);
     if (t_idx >= args.ntiles) return;
     const Tile tile = args.tiles[t_idx];
     const LatticeRec& R = args.recs[tile.lat];
-    // Blown-up lattices are frozen.  The flag can be raised by other blocks while
-    // this one starts, so one thread reads it and the whole block follows.
+    // Blown-up lattices are frozen: steps skip them.  The flag can be raised by
+    // other blocks while this one starts, so one thread reads it and the whole
+    // block follows.  A read-out, which stores no populations, covers every tile.
     __shared__ unsigned s_skip;
-    if (threadIdx.x == 0) s_skip = __atomic_load_n(args.status + tile.lat, __ATOMIC_RELAXED);
+    if (threadIdx.x == 0) {
+        s_skip = __atomic_load_n(args.status + tile.lat, __ATOMIC_RELAXED);
+        s_ured[NT / 64] = 0u;
+    }
     __syncthreads();
-    if (s_skip != 0u) return;
+    if (MODE == kStep && s_skip != 0u) return;
 
     const int nx = R.nx, ny = R.ny, nz = R.nz;
     const int N = nx * ny * nz, NXY = nx * ny;
@@ -622,10 +626,6 @@ hipError_t launch3_t(const StepArgs& a, int grid, hipStream_t s, int mode) {
     const dim3 g(grid), b(BX * BY);
     if (mode == kFields)
         hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kFields, false>), g, b, 0, s, a);
-    else if (mode == kStepDiag && a.write_through)
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag, true>), g, b, 0, s, a);
-    else if (mode == kStepDiag)
-        hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStepDiag, false>), g, b, 0, s, a);
     else if (a.write_through)
         hipLaunchKernelGGL((d3q19::step_kernel<S, T, V, BX, BY, kStep, true>), g, b, 0, s, a);
     else

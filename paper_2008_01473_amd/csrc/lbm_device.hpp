@@ -224,21 +224,52 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles_per_xcd) {
     return (b & 7) * tiles_per_xcd + (b >> 3);
 }
 
+// Wave reductions without LDS traffic: four DPP butterflies inside each 16-lane
+// row (quad permutations [1,0,3,2] and [2,3,0,1], then the half-row and row
+// mirrors) leave every lane holding its row's result, and the rows are combined
+// from lanes 0, 16, 32 and 48 in that order.  A lane and its partner compute
+// op(a, b) and op(b, a), equal for these commutative operations, so the result
+// does not depend on the lane.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = dpp_u32<CTRL>((unsigned)u), hi = dpp_u32<CTRL>((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+    v = op(v, dpp_f64<0xB1>(v));         // quad_perm [1,0,3,2]
+    v = op(v, dpp_f64<0x4E>(v));         // quad_perm [2,3,0,1]
+    v = op(v, dpp_f64<0x141>(v));        // row_half_mirror
+    v = op(v, dpp_f64<0x140>(v));        // row_mirror
+    return op(op(lane_f64(v, 0), lane_f64(v, 16)), op(lane_f64(v, 32), lane_f64(v, 48)));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_reduce(v, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
 }
 __device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 __device__ __forceinline__ unsigned wave_or(unsigned v) {
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-    return v;
+    v |= dpp_u32<0xB1>(v);
+    v |= dpp_u32<0x4E>(v);
+    v |= dpp_u32<0x141>(v);
+    v |= dpp_u32<0x140>(v);
+    return ((unsigned)__builtin_amdgcn_readlane((int)v, 0) | (unsigned)__builtin_amdgcn_readlane((int)v, 16)) |
+           ((unsigned)__builtin_amdgcn_readlane((int)v, 32) | (unsigned)__builtin_amdgcn_readlane((int)v, 48));
 }
 
 // Per-thread diagnostics accumulator, reduced over the block in a fixed order.
@@ -248,43 +279,43 @@ struct DiagAcc {
     unsigned status = 0;
 };
 
-// Waves W0 .. NT/64 - 1 hold the tile's contributions (the others only pass the
-// barrier).  Returns the tile's status bits in thread 64 W0 (the value it stored),
-// so that the caller need not read the record back from memory; 0 elsewhere.
-template <int NT, int W0 = 0>
+// Every wave puts its reduction in LDS and counts its arrival in uscratch[NW]
+// (zero on entry); the wave that arrives last sums the slots in wave order (the
+// same order whichever wave that is) and stores the record.  No wave waits at a
+// barrier, so none waits for the others' global stores to complete.  Returns the
+// tile's status bits in lane 0 of that wave (the value it stored), 0 elsewhere.
+template <int NT>
 __device__ __forceinline__ unsigned block_reduce_store(const DiagAcc& a, DiagPartial* out, double* scratch,
                                                        unsigned* uscratch) {
     constexpr int NW = NT / 64;
-    static_assert(W0 >= 0 && W0 < NW, "no wave holds the contributions");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w >= W0) {
-        double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
-                       wave_max(a.umax2), wave_min(a.mumin), wave_max(a.mumax)};
-        unsigned st = wave_or(a.status);
-        if (lane == 0) {
-            for (int k = 0; k < 7; ++k) scratch[k * NW + w] = v[k];
-            uscratch[w] = st;
-        }
+    double v[7] = {wave_sum(a.mass), wave_sum(a.mx), wave_sum(a.my), wave_sum(a.mz),
+                   wave_max(a.umax2), wave_min(a.mumin), wave_max(a.mumax)};
+    const unsigned st = wave_or(a.status);
+    if (lane != 0) return 0u;
+    for (int k = 0; k < 7; ++k) scratch[k * NW + w] = v[k];
+    uscratch[w] = st;
+    // the slots are in LDS before the arrival counts (an LDS-only fence: the
+    // wave's global stores stay in flight)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    const unsigned before = __hip_atomic_fetch_add(uscratch + NW, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (before != (unsigned)(NW - 1)) return 0u;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    DiagPartial p;
+    p.mass = 0; p.momx = 0; p.momy = 0; p.momz = 0;
+    p.umax2 = 0; p.mumin = 1e300; p.mumax = -1e300; p.status = 0; p.pad = 0;
+    for (int i = 0; i < NW; ++i) {
+        p.mass += scratch[0 * NW + i];
+        p.momx += scratch[1 * NW + i];
+        p.momy += scratch[2 * NW + i];
+        p.momz += scratch[3 * NW + i];
+        p.umax2 = fmax(p.umax2, scratch[4 * NW + i]);
+        p.mumin = fmin(p.mumin, scratch[5 * NW + i]);
+        p.mumax = fmax(p.mumax, scratch[6 * NW + i]);
+        p.status |= uscratch[i];
     }
-    __syncthreads();
-    if (threadIdx.x == 64 * W0) {
-        DiagPartial p;
-        p.mass = 0; p.momx = 0; p.momy = 0; p.momz = 0;
-        p.umax2 = 0; p.mumin = 1e300; p.mumax = -1e300; p.status = 0; p.pad = 0;
-        for (int i = W0; i < NW; ++i) {
-            p.mass += scratch[0 * NW + i];
-            p.momx += scratch[1 * NW + i];
-            p.momy += scratch[2 * NW + i];
-            p.momz += scratch[3 * NW + i];
-            p.umax2 = fmax(p.umax2, scratch[4 * NW + i]);
-            p.mumin = fmin(p.mumin, scratch[5 * NW + i]);
-            p.mumax = fmax(p.mumax, scratch[6 * NW + i]);
-            p.status |= uscratch[i];
-        }
-        *out = p;
-        return p.status;
-    }
-    return 0u;
+    *out = p;
+    return p.status;
 }
 
 // BGK update of a pair of opposite velocities e and -e (same weight w):

@@ -19,8 +19,7 @@ enum Variant : int {
 // What a step-kernel launch does at its output nodes.
 enum Mode : int {
     kStep = 0,         // collide and store; only the blow-up flags are checked
-    kStepDiag = 1,     // collide and store, and write the per-tile diagnostics
-    kFields = 2        // write rho, u, mu (and the diagnostics) of the current time level
+    kFields = 1        // write rho, u, mu (any may be absent) and the per-tile diagnostics
 };
 
 // Per-lattice record, uploaded once at bind time.

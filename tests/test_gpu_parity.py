@@ -223,7 +223,7 @@ def test_reported_blowup_leaves_the_plan_until_reinit():
     sim.step(10)
     d1 = sim.diagnostics()
     assert d1[0]["status"] != 0 and d1[1]["status"] == 0
-    assert sim.diagnostics() == d1
+    assert repr(sim.diagnostics()) == repr(d1)          # NaNs of the blown-up state included
     off = sim.offsets()[1]
     frozen = sim.get_f()[:, :off].cpu()
     sim.step(7)
