@@ -178,3 +178,46 @@ def test_fp32_storage_diagnostics(lattice):
         r = 5.0
     _run_and_check([p], [r], 4, 2e-5, f"{lattice} fp32")
     assert math.isfinite(r)
+
+
+def _next_supported_shape(sim):
+    cur = _lib.lib().lbm_get_tile_shape(sim.h)
+    for k in range(1, sim.num_tile_shapes()):
+        try:
+            sim.set_tile_shape((cur + k) % sim.num_tile_shapes())
+            return
+        except _lib.LBMError as e:
+            assert e.code == _lib.LBM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("lattice,graphs", [("D2Q9", True), ("D2Q9", False), ("D3Q19", True)])
+def test_diagnostics_after_steps_read_the_last_input(lattice, graphs):
+    """After lbm_step(n) the diagnostics are reduced from the last step's input,
+    which the second buffer holds: bit for bit those lbm_moments gives on a copy
+    stepped n - 1 times, for odd and even n, and after a change of tile shape
+    between the steps and the call."""
+    if lattice == "D2Q9":
+        p = runtime.params("D2Q9", 70, 37, 1, eos="CS", T_over_Tc=0.85, kappa=0.02, tau=0.8)
+        r = 9.0
+    else:
+        p = runtime.params("D3Q19", 20, 18, 22, eos="vdW", T_over_Tc=0.85, kappa=0.02, tau=1.0)
+        r = 5.0
+    rho0, u0 = _inputs(p, r, seed=5)
+    for n in (5, 6):
+        for retile in (False, True):
+            print(f"case {lattice} graphs={graphs} n={n} retile={retile}", flush=True)
+            a, b = runtime.LBM([p]), runtime.LBM([p])
+            for sim in (a, b):
+                sim.use_graphs(graphs)
+                sim.init(rho0.reshape(-1), u0.reshape(len(u0), -1).reshape(-1))
+            a.step(n)
+            if retile:
+                _next_supported_shape(a)
+            b.set_tile_shape(_lib.lib().lbm_get_tile_shape(a.h))
+            b.step(n - 1)
+            b.moments()
+            da, db = a.diagnostics(), b.diagnostics()
+            assert da[0]["step"] == db[0]["step"] == n - 1
+            assert repr(da) == repr(db)
+            a.close()
+            b.close()
