@@ -701,6 +701,18 @@ int lbm_moments(lbm_ctx* h, double* rho, double* u, double* mu) {
     return LBM_OK;
 }
 
+// The read-out of the last step's input (the other buffer) into the per-tile
+// partials, if lbm_step left it to be done; enqueued with the lattice records the
+// steps used.
+static int reduce_pending_diag(lbm_ctx* h) {
+    if (!h->diag_pending) return LBM_OK;
+    StepArgs a = base_args(h);
+    a.src = h->buf[h->cur ^ 1];
+    HIP_TRY(launch_step(h, a, kFields, h->stream));
+    h->diag_pending = false;
+    return LBM_OK;
+}
+
 int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
     if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
     if (!h->inited || h->t_diag < 0) return fail(LBM_ERR_STATE, "no diagnostics yet (step or moments first)");
@@ -709,13 +721,7 @@ int lbm_diagnostics(lbm_ctx* h, lbm_diag* out) {
     if (h->diag_cache_valid) {
         tmp = h->diag_cache;
     } else {
-        if (h->diag_pending) {
-            // the read-out of the last step's input (the other buffer): per-tile partials only
-            StepArgs a = base_args(h);
-            a.src = h->buf[h->cur ^ 1];
-            HIP_TRY(launch_step(h, a, kFields, h->stream));
-            h->diag_pending = false;
-        }
+        if (int rc0 = reduce_pending_diag(h); rc0 != LBM_OK) return rc0;
         HIP_TRY(launch_finalize(h->d_partial(), h->d_recs(), h->d_status(), h->d_diag(), n, h->stream));
         HIP_TRY(hipMemcpyAsync(tmp.data(), h->d_diag(), n * sizeof(DiagOut), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -966,6 +972,10 @@ int lbm_autotune(lbm_ctx* h, int steps, void* scratch) {
 int lbm_set_physics(lbm_ctx* h, int i, double kappa, double T_over_Tc) {
     if (!h || i < 0 || i >= (int)h->recs.size()) return fail(LBM_ERR_ARG, "bad handle or lattice index");
     if (!(kappa >= 0) || !(T_over_Tc > 0)) return fail(LBM_ERR_ARG, "kappa >= 0 and T_over_Tc > 0 required");
+    // diagnostics still owed for the last step are reduced with the physics it used
+    if (h->bound) {
+        if (int rc0 = reduce_pending_diag(h); rc0 != LBM_OK) return rc0;
+    }
     lbm_params& p = h->params[i];
     p.kappa = kappa;
     p.T_over_Tc = T_over_Tc;

@@ -221,3 +221,25 @@ def test_diagnostics_after_steps_read_the_last_input(lattice, graphs):
             assert repr(da) == repr(db)
             a.close()
             b.close()
+
+
+def test_diagnostics_owed_by_steps_use_the_physics_of_those_steps():
+    """A change of kappa and T/Tc between lbm_step and lbm_diagnostics does not
+    reach the diagnostics of the last step's input: they are those of a copy
+    stepped with the old physics and read out before any change."""
+    p = runtime.params("D2Q9", 70, 37, 1, eos="CS", T_over_Tc=0.85, kappa=0.02, tau=0.8)
+    rho0, u0 = _inputs(p, 9.0, seed=7)
+    a, b = runtime.LBM([p]), runtime.LBM([p])
+    for sim in (a, b):
+        sim.init(rho0.reshape(-1), u0.reshape(-1))
+    b.set_tile_shape(_lib.lib().lbm_get_tile_shape(a.h))
+    a.step(6)
+    _lib.check(_lib.lib().lbm_set_physics(a.h, 0, 0.03, 0.9), "lbm_set_physics")
+    da = a.diagnostics()
+    b.step(5)
+    b.moments()
+    db = b.diagnostics()
+    assert da[0]["step"] == db[0]["step"] == 5
+    assert repr(da) == repr(db)
+    a.close()
+    b.close()
